@@ -1,0 +1,28 @@
+"""Plain, slow, FP64 CPU oracle for the dealiased nonlinear term of 3D periodic
+incompressible Navier-Stokes and for the Runge-Kutta schemes that call it.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or link
+anything in this package; only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+path: every formula here is written out from the paper (arXiv 2603.08892,
+"Aliasing and phase shifting in pseudo-spectral simulations of the
+incompressible Navier-Stokes equations") in NumPy/SciPy, in float64.
+
+Modules
+-------
+grid       wavenumbers, truncation thresholds and masks, Hermitian weights, shells
+transforms forward (1/N per axis) and inverse (unnormalised) real FFTs
+nonlinear  phase shift, curl, projection, u x omega, shift averages, padded product,
+           and the transpose of the linearised nonlinear term (for the adjoint)
+schemes    integrating-factor Euler, midpoint RK2, Lawson RK4, phase-shifted RK2
+           (exact / approx / random, optional split forcing) and the step adjoint
+spectra    shell, 1D, dissipation and transfer spectra; totals
+forcing    SplitMix64 counter-based draws, forcing amplitudes and injection scaling
+nl1d       the 1D quadratic model dS/dt = -S^2
+
+Parity status: every function is pinned by at least one test in
+``tests/test_oracle_*.py`` except the forcing draw itself (parity unpinned against
+the paper, which gives no forcing formula; only its injection rate is pinned).
+"""
+
+from . import grid, transforms, nonlinear, schemes, spectra, forcing, nl1d  # noqa: F401
