@@ -1,0 +1,187 @@
+/*
+ * ns.h -- C ABI of libns.so: the dealiased nonlinear term of 3D periodic
+ * incompressible Navier-Stokes and the Runge-Kutta schemes built on it, on one
+ * AMD Instinct MI355X (gfx950).  Method: Lambert, Reneuve & Augier,
+ * "Aliasing and phase shifting in pseudo-spectral simulations of the
+ * incompressible Navier-Stokes equations" (arXiv 2603.08892).
+ *
+ * Problem (Eq. base-eq): dS/dt = sigma S + N(S), S = u_hat the spectral velocity,
+ * sigma(k) = -nu |k|^2, N(S) the divergence-free projection of the advective term,
+ * evaluated pseudo-spectrally in rotational form, N = M P FFT(u x omega).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Box 2*pi, N points per direction, integer wavenumbers.  Forward transform
+ * u_hat(k) = N^-3 sum_x u(x) exp(-i k.x), inverse unnormalised (Eqs. u_fft_1d,
+ * u_expansion_1d and supplementary Eq. dft_def).
+ *
+ * Spectral field layout ("state layout"): 3 components, each [N][N][N/2+1]
+ * complex in C order, interleaved (re, im); component stride N*N*(N/2+1)
+ * complex.  Axis 0 is k_x, axis 1 is k_y, both in FFT index order (index i < N/2
+ * holds k = i, else k = i - N); axis 2 is k_z = 0..N/2, contiguous.  Element type
+ * is float2 for NS_FP32 and double2 for NS_FP64 (cfg.precision).
+ *
+ * Truncation (Sec. "Standard dealiasing with truncation", Fig. 1): with
+ * k_max = ct*N/2, the sphere keeps integer |k|^2 <= K2max, K2max the largest
+ * integer strictly below k_max^2; the cube keeps max_i |k_i| <= Kmax, Kmax the
+ * largest integer strictly below k_max.  A real value within a relative 1e-9 of
+ * an integer is taken as that integer (so C_t = 2/3 at N = 192 keeps K2max = 4095).
+ * States live in the retained set: on input every mode outside it is ignored
+ * (treated as zero); on output every mode outside it is zero.
+ *
+ * Shifts are in grid-spacing units: s = (sx, sy, sz) means Delta = s*2*pi/N and the
+ * phase factor exp(2 pi i k.s / N) (Eqs. shift_operator, shift_operator_3d).
+ *
+ * Memory and streams: every field pointer is a device pointer, 256-byte aligned,
+ * owned by the caller; the library allocates no device memory.  The caller
+ * provides one workspace of ns_workspace_bytes() bytes at ns_init; the context
+ * borrows it and must not outlive it.  Work is enqueued on cfg.stream (a
+ * hipStream_t; NULL = the null stream) and the calls return without waiting,
+ * except ns_spectra, which waits for its few-KB result.  A context is not thread
+ * safe; calls that overlap on one context race.
+ *
+ * Errors: every call returns ns_status.  Arguments are checked on the host before
+ * any HIP call.  Asynchronous device faults surface at a later call as
+ * NS_ERR_HIP.  ns_last_error gives a message for the last failure on a context
+ * (or, for ctx == NULL, for the last ns_init/ns_workspace_bytes failure of the
+ * calling thread).
+ */
+#ifndef NS_H_
+#define NS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_ctx ns_ctx;
+
+typedef enum {
+  NS_OK = 0,
+  NS_ERR_ARG = 1,       /* invalid argument (null/misaligned pointer, bad size or value) */
+  NS_ERR_SIZE = 2,      /* workspace too small */
+  NS_ERR_HIP = 3,       /* a HIP runtime call failed (possibly an earlier async fault) */
+  NS_ERR_STATE = 4,     /* context unusable */
+  NS_ERR_NONFINITE = 5  /* ns_spectra found a NaN or Inf in its input */
+} ns_status;
+
+typedef enum { NS_FP32 = 0, NS_FP64 = 1 } ns_precision;
+typedef enum { NS_MASK_SPHERE = 0, NS_MASK_CUBE = 1 } ns_mask;
+
+/* Phase-shift RK2 variants (Sec. "Extension to the multidimensional case"). */
+typedef enum {
+  NS_PS_EXACT = 0,  /* midpoint RK2, every evaluation the average over shifts 0 and (1/2,1/2,1/2) */
+  NS_PS_APPROX = 1, /* Heun/Rogallo with alpha = 0, beta = (1/2,1/2,1/2) */
+  NS_PS_RANDOM = 2  /* Heun/Rogallo with alpha ~ U[0,1)^3 per step, beta = alpha + 1/2 (mod 1) */
+} ns_ps_variant;
+
+typedef struct {
+  int32_t n;          /* grid points per direction: 2^a 3^b 5^c, a >= 1, 8 <= n <= 1024 */
+  int32_t precision;  /* ns_precision of every field */
+  int32_t mask;       /* ns_mask */
+  int32_t reserved;   /* must be 0 */
+  double nu;          /* kinematic viscosity, >= 0 */
+  double ct;          /* truncation coefficient, 0 < ct <= 1 */
+  uint64_t seed;      /* seed of the per-step random shifts (NS_PS_RANDOM, alphas == NULL) */
+  void* stream;       /* hipStream_t on which all work is enqueued */
+} ns_config;
+
+/* Forcing of the "split" phase-shift scheme (Eq. forcing-eq): a divergence-free
+ * random field on the shell k2_lo <= |k|^2 <= k2_hi (only 4..9 supported, the
+ * 96 modes of 2 <= |k| <= 3), redrawn every step from SplitMix64(seed, step) and
+ * scaled so that the step injects energy at rate `injection`:
+ * a sum w Re(conj(u0).g) + a^2 dt/2 sum w |g|^2 = injection, O = a g, and O is
+ * added to both stages (O0 = O1 = O). */
+typedef struct {
+  int32_t k2_lo, k2_hi;  /* must be 4 and 9 */
+  double injection;      /* energy injection rate, > 0 */
+  uint64_t seed;
+} ns_forcing;
+
+/* Host-side outputs of ns_spectra; every pointer may be NULL (not written).
+ * n_shell = ns_num_shells(n).  FP64 throughout. */
+typedef struct {
+  double* e_shell;  /* [n_shell] E(n) = 1/2 sum_{shell n} w |u|^2, shell: n(n-1) < |k|^2 <= n(n+1) */
+  double* d_shell;  /* [n_shell] D(n) = nu sum_{shell n} w |k|^2 |u|^2 (dissipation spectrum) */
+  double* t_shell;  /* [n_shell] T(n) = sum_{shell n} w Re(conj(u).N) (zero if n_hat is NULL) */
+  double* e_1d;     /* [3][n/2+1] E_i(m) = 1/2 sum_{|k_i| = m} w |u|^2 */
+  double* totals;   /* [5] E, eps = nu sum w |k|^2 |u|^2, H = 1/2 sum w Re(conj(u).omega), T, #nonfinite */
+} ns_spectra_out;
+
+/* Flags of ns_nonlinear. */
+#define NS_NL_PS_AVG 1  /* return 1/2 [N(u; 0) + N(u; (1/2,1/2,1/2))] (Eq. sum_ps_non_ps, 3D shift); `shift` ignored */
+
+/* Bytes of device workspace needed for cfg (0 if cfg is invalid). */
+size_t ns_workspace_bytes(const ns_config* cfg);
+
+/* Number of shells of the spectra for grid size n. */
+int32_t ns_num_shells(int32_t n);
+
+/* Largest retained |k|^2 (sphere) or |k_i| (cube) for cfg, -1 if cfg is invalid. */
+int64_t ns_retained_bound(const ns_config* cfg);
+
+/* Create a context on `workspace` (device memory, >= ns_workspace_bytes(cfg)
+ * bytes, 256-byte aligned).  Builds FFT plans and uploads FP64-generated
+ * twiddles; synchronous.  *out is set only on NS_OK. */
+ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx** out);
+
+/* Release a context (host memory only; the workspace stays the caller's). */
+ns_status ns_destroy(ns_ctx* ctx);
+
+const char* ns_last_error(const ns_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+ns_status ns_set_stream(ns_ctx* ctx, void* stream);
+
+/* One evaluation of the nonlinear term (Sec. "Aliasing description" for the
+ * pseudo-spectral product, Eqs. shift_operator_3d and sum_ps_non_ps for the shift):
+ *   n_hat = M conj(phi) P FFT( IFFT(phi M u_hat) x IFFT(i k x phi M u_hat) ),
+ * phi = exp(2 pi i k.shift/N); shift NULL = unshifted.  u_hat and n_hat are
+ * state-layout device arrays and must not overlap.  n_hat is fully written
+ * (zero outside the retained set and at k = 0). */
+ns_status ns_nonlinear(ns_ctx* ctx, const void* u_hat, void* n_hat, const double shift[3],
+                       int32_t flags);
+
+/* nsteps steps of classical RK4 in integrating-factor (Lawson) form, unshifted
+ * (the 2/3-truncation baseline of Tables I-V when cfg.ct = 2/3), in place on the
+ * state u_hat.  dt > 0, nsteps >= 0. */
+ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps);
+
+/* nsteps steps of phase-shift RK2 (Eqs. Rogallo1981 and its 3D form; split
+ * forcing of Eq. forcing-eq when forcing != NULL, Heun variants only), in
+ * place on u_hat.  variant: ns_ps_variant.  alphas: host array [nsteps][3] of
+ * first-stage shifts for NS_PS_RANDOM, or NULL to draw them as
+ * alpha_i = SplitMix64 uniform (cfg.seed, step0 + s, i); ignored by the other
+ * variants.  step0 keys the random draws (shifts and forcing) of the first step,
+ * so that runs can be split and resumed exactly.
+ *   exact:  S_h = E_{dt/2}(S0 + dt/2 A(S0)), S = E_dt S0 + dt E_{dt/2} A(S_h),
+ *           A = 1/2 [N(.;0) + N(.;1/2)]
+ *   heun:   S1 = E_dt(S0 + dt (N(S0;alpha) + O)),
+ *           S = E_dt S0 + dt/2 E_{dt/2} (N(S0;alpha) + N(S1;beta) + 2 O)
+ * with E_tau = exp(-nu |k|^2 tau). */
+ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps,
+                                 int32_t variant, const double* alphas,
+                                 const ns_forcing* forcing, int64_t step0);
+
+/* FP64 spectra and totals of the state u_hat (and the transfer with n_hat when
+ * non-NULL), Sec. "3D flow: Taylor-Green vortices".  Waits for the result.
+ * Returns NS_ERR_NONFINITE (outputs still written) if any entry of u_hat or
+ * n_hat is NaN or Inf. */
+ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out);
+
+/* Transpose of the linearised phase-shift RK2 step at state u_hat0 (no forcing):
+ * lam holds dJ/dS_{n+1} on entry and dJ/dS_n on return, both with respect to the
+ * Parseval inner product <a,b> = sum_k w Re(conj(a).b) (w = 1 on the k_z = 0 and
+ * N/2 planes, 2 elsewhere); multiply by w for the gradient of the real and
+ * imaginary parts taken as independent variables.  alpha: the first-stage shift
+ * used by the forward step (NS_PS_RANDOM; NULL for the other variants). */
+ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt,
+                                int32_t variant, const double alpha[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NS_H_ */

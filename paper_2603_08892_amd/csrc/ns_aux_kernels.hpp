@@ -1,0 +1,202 @@
+// ns_aux_kernels.hpp -- FP64 spectra reduction and the large-scale forcing draw (gfx950).
+#pragma once
+
+#include "ns_kernels.hpp"
+
+namespace ns {
+
+// Shell of an integer |k|^2: smallest n with n(n+1) >= k^2, i.e. n(n-1) < k^2 <= n(n+1).
+__device__ __forceinline__ int shell_of(long long k2) {
+  const int r = isqrt_ll(k2);
+  return ((long long)r * (r + 1) >= k2) ? r : r + 1;
+}
+
+// Bin layout of one partial: [0, nsh) E, [nsh, 2nsh) D, [2nsh, 3nsh) T,
+// then 3 x h one-dimensional energies, then totals E, eps, H, T, nonfinite.
+// Pass 1: every block accumulates its grid-stride share of the modes into LDS
+// bins (FP64) and writes them to partials[block].
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_spectra(const Cx<R>* __restrict__ u, const Cx<R>* __restrict__ nh, double nu, int n, int h,
+          int nsh, long long comp, double* __restrict__ partials) {
+  extern __shared__ double bins[];
+  const int nb = 3 * nsh + 3 * h + 5;
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) bins[t] = 0.0;
+  __syncthreads();
+  double tE = 0, tD = 0, tH = 0, tT = 0;
+  unsigned bad = 0;
+  const long long total = comp;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int kz = (int)(idx % h);
+    const long long r2 = idx / h;
+    const int yi = (int)(r2 % n), xi = (int)(r2 / n);
+    const int kx = kval(xi, n), ky = kval(yi, n);
+    const double w = (kz == 0 || 2 * kz == n) ? 1.0 : 2.0;
+    const Cx<R> a0 = u[idx], a1 = u[comp + idx], a2 = u[2 * comp + idx];
+    double ar[3] = {(double)a0.re, (double)a1.re, (double)a2.re};
+    double ai[3] = {(double)a0.im, (double)a1.im, (double)a2.im};
+    bool fin = true;
+    for (int c = 0; c < 3; ++c) fin = fin && isfinite(ar[c]) && isfinite(ai[c]);
+    double t = 0.0;
+    if (nh != nullptr) {
+      for (int c = 0; c < 3; ++c) {
+        const Cx<R> b = nh[c * comp + idx];
+        fin = fin && isfinite((double)b.re) && isfinite((double)b.im);
+        t += ar[c] * (double)b.re + ai[c] * (double)b.im;
+      }
+      t *= w;
+    }
+    if (!fin) { ++bad; continue; }
+    const double e = 0.5 * w * (ar[0] * ar[0] + ai[0] * ai[0] + ar[1] * ar[1] + ai[1] * ai[1] +
+                                ar[2] * ar[2] + ai[2] * ai[2]);
+    if (e == 0.0 && t == 0.0) continue;
+    const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
+    const double d = 2.0 * nu * (double)k2 * e;
+    // helicity density: with u = a + i b, Re(conj(u).(i k x u)) = 2 k.(a x b), so
+    // 1/2 w Re(conj(u).omega) = w k.(a x b)
+    const double cxr = ar[1] * ai[2] - ar[2] * ai[1];
+    const double cyr = ar[2] * ai[0] - ar[0] * ai[2];
+    const double czr = ar[0] * ai[1] - ar[1] * ai[0];
+    const double hd = w * ((double)kx * cxr + (double)ky * cyr + (double)kz * czr);
+    const int s = shell_of(k2);
+    atomicAdd(&bins[s], e);
+    atomicAdd(&bins[nsh + s], d);
+    if (nh != nullptr) atomicAdd(&bins[2 * nsh + s], t);
+    atomicAdd(&bins[3 * nsh + abs(kx)], e);
+    atomicAdd(&bins[3 * nsh + h + abs(ky)], e);
+    atomicAdd(&bins[3 * nsh + 2 * h + kz], e);
+    tE += e; tD += d; tH += hd; tT += t;
+  }
+  // totals: wave reduction then one LDS atomic per wave
+  for (int off = 32; off > 0; off >>= 1) {
+    tE += __shfl_down(tE, off);
+    tD += __shfl_down(tD, off);
+    tH += __shfl_down(tH, off);
+    tT += __shfl_down(tT, off);
+    bad += __shfl_down(bad, off);
+  }
+  const int tot = 3 * nsh + 3 * h;
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&bins[tot + 0], tE);
+    atomicAdd(&bins[tot + 1], tD);
+    atomicAdd(&bins[tot + 2], tH);
+    atomicAdd(&bins[tot + 3], tT);
+    atomicAdd(&bins[tot + 4], (double)bad);
+  }
+  __syncthreads();
+  double* out = partials + (long long)blockIdx.x * nb;
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) out[t] = bins[t];
+}
+
+// Pass 2: fixed-order sum over the blocks' partials, one thread per bin.
+__global__ void k_spectra_sum(const double* __restrict__ partials, int nblocks, int nb,
+                              double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partials[(long long)b * nb + t];
+  out[t] = s;
+}
+
+// ------------------------------------------------------------------ forcing
+// SplitMix64 (Steele, Lea & Flood 2014) used counter-based:
+// stream(seed, step) = mix(seed + G (step + 1)), draw j = mix(stream + G (j + 1)),
+// uniform = (draw >> 11) 2^-53; Box-Muller on pairs (u1, u2).
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double sm64_uniform(uint64_t seed, long long step, long long j) {
+  const uint64_t G = 0x9E3779B97F4A7C15ull;
+  const uint64_t s = sm64_mix(seed + G * (uint64_t)(step + 1));
+  return (double)(sm64_mix(s + G * (uint64_t)(j + 1)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Forced modes 4 <= |k|^2 <= 9 in draw order (k_z 0..3, then k_x, k_y from -3 to 3;
+// on k_z = 0 only k_x > 0, or k_x = 0 and k_y > 0): 48 independent modes.
+__device__ __forceinline__ int forcing_mode(int i, int* kx, int* ky, int* kz) {
+  int c = 0;
+  for (int z = 0; z <= 3; ++z)
+    for (int x = -3; x <= 3; ++x)
+      for (int y = -3; y <= 3; ++y) {
+        const int k2 = x * x + y * y + z * z;
+        if (k2 < 4 || k2 > 9) continue;
+        if (z == 0 && !(x > 0 || (x == 0 && y > 0))) continue;
+        if (c == i) { *kx = x; *ky = y; *kz = z; return 1; }
+        ++c;
+      }
+  return 0;
+}
+
+// One block of 64 threads: draw g for `step`, project it, scale it to inject
+// energy at rate `inj` over a step dt from state u, write the dense table
+// force[c][k_x+3][k_y+3][k_z] (k_z <= 3).
+template <typename R>
+__global__ void __launch_bounds__(64)
+k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int h, long long comp,
+          uint64_t seed, long long step, double dt, double inj) {
+  __shared__ double gre[48][3], gim[48][3], pb[48], pg[48];
+  __shared__ double amp;
+  const int i = threadIdx.x;
+  for (int t = i; t < 3 * 196; t += blockDim.x) force[t] = cx(R(0), R(0));
+  if (i < 48) {
+    int kx, ky, kz;
+    forcing_mode(i, &kx, &ky, &kz);
+    double vr[3], vi[3];
+    for (int c = 0; c < 3; ++c) {
+      const long long p = 3 * i + c;
+      const double u1 = sm64_uniform(seed, step, 2 * p);
+      const double u2 = sm64_uniform(seed, step, 2 * p + 1);
+      const double r = sqrt(-2.0 * log(1.0 - u1));
+      double sn, cs;
+      sincospi(2.0 * u2, &sn, &cs);
+      vr[c] = r * cs;
+      vi[c] = r * sn;
+    }
+    const double k2 = (double)(kx * kx + ky * ky + kz * kz);
+    const double dr = (kx * vr[0] + ky * vr[1] + kz * vr[2]) / k2;
+    const double di = (kx * vi[0] + ky * vi[1] + kz * vi[2]) / k2;
+    vr[0] -= kx * dr; vr[1] -= ky * dr; vr[2] -= kz * dr;
+    vi[0] -= kx * di; vi[1] -= ky * di; vi[2] -= kz * di;
+    // B and G contributions of the stored half-spectrum entries of this mode
+    const long long idx = ((long long)((kx + n) % n) * n + (ky + n) % n) * h + kz;
+    double b = 0, g2 = 0;
+    const double w = (kz == 0) ? 1.0 : 2.0;
+    for (int c = 0; c < 3; ++c) {
+      const Cx<R> a = u[c * comp + idx];
+      b += w * ((double)a.re * vr[c] + (double)a.im * vi[c]);
+      g2 += w * (vr[c] * vr[c] + vi[c] * vi[c]);
+    }
+    if (kz == 0) {  // the partner -k holds conj(g)
+      const long long idp = ((long long)((-kx + n) % n) * n + (-ky + n) % n) * h;
+      for (int c = 0; c < 3; ++c) {
+        const Cx<R> a = u[c * comp + idp];
+        b += (double)a.re * vr[c] - (double)a.im * vi[c];
+        g2 += vr[c] * vr[c] + vi[c] * vi[c];
+      }
+    }
+    for (int c = 0; c < 3; ++c) { gre[i][c] = vr[c]; gim[i][c] = vi[c]; }
+    pb[i] = b;
+    pg[i] = g2;
+  }
+  __syncthreads();
+  if (i == 0) {
+    double B = 0, G = 0;
+    for (int m = 0; m < 48; ++m) { B += pb[m]; G += pg[m]; }
+    amp = 2.0 * inj / (B + sqrt(B * B + 2.0 * dt * G * inj));
+  }
+  __syncthreads();
+  if (i < 48) {
+    int kx, ky, kz;
+    forcing_mode(i, &kx, &ky, &kz);
+    for (int c = 0; c < 3; ++c) {
+      const double re = amp * gre[i][c], im = amp * gim[i][c];
+      force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz] = cx(R(re), R(im));
+      if (kz == 0) force[c * 196 + ((-kx + 3) * 7 + (-ky + 3)) * 4] = cx(R(re), R(-im));
+    }
+  }
+}
+
+}  // namespace ns

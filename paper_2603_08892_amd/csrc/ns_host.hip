@@ -1,0 +1,628 @@
+// ns_host.hip -- implementation of the C ABI declared in include/ns.h.
+//
+// Host side: argument checks, geometry of the pruned transforms, FFT plans,
+// workspace layout, and the launch sequences of one nonlinear-term evaluation
+// and of the Runge-Kutta schemes (Eq. base-eq integrated with exact integrating
+// factors; RK4 in Lawson form, RK2 phase-shift exact / approx / random).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ns.h"
+#include "ns_aux_kernels.hpp"
+
+using ns::Cx;
+using ns::EpiArgs;
+using ns::FftPlan;
+using ns::Geom;
+
+namespace {
+
+constexpr int kEpt = 8;     // points per thread in the strided passes
+constexpr int kEptZ = 16;   // points per thread in the contiguous (z) pass
+constexpr size_t kAlign = 256;
+constexpr int kSpecBlocks = 256;
+
+thread_local std::string g_last_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Largest integer strictly below x, a value within relative 1e-9 of an integer
+// being taken as that integer.
+long long largest_int_below(double x) {
+  const double eps = 1e-9 * std::fmax(1.0, std::fabs(x));
+  return (long long)std::ceil(x - eps) - 1;
+}
+
+bool factor_ok(int n, std::vector<int>* radices) {
+  if (n < 8 || n > 1024) return false;
+  int m = n, a = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  if (a < 1) return false;
+  std::vector<int> r;
+  while (a >= 3 && a != 4) { r.push_back(8); a -= 3; }
+  if (a == 4) { r.push_back(4); r.push_back(4); a = 0; }
+  if (a == 2) { r.push_back(4); a = 0; }
+  if (a == 1) { r.push_back(2); a = 0; }
+  while (m % 3 == 0) { r.push_back(3); m /= 3; }
+  while (m % 5 == 0) { r.push_back(5); m /= 5; }
+  if (m != 1 || (int)r.size() > ns::kMaxStages) return false;
+  if (radices) *radices = r;
+  return true;
+}
+
+struct Layout {
+  Geom g;
+  FftPlan plan;
+  int elem;          // bytes per complex element
+  int tx;            // threads of the strided passes
+  int ntz;           // k_z tiles over [0, kzn)
+  int ntzf;          // k_z tiles over [0, N/2]
+  int pz, tz;        // lines per block and threads of the z pass
+  long long k2top;   // largest retained |k|^2
+  int nsh, nbins;
+  std::vector<int2> tiles;
+  size_t off_tw, off_ph, off_etab, off_force, off_tiles, off_w, off_s, off_a, off_spec, off_specout;
+  size_t total;
+};
+
+bool retained_host(const Geom& g, long long kx, long long ky, long long kz) {
+  if (g.mask == 0) return kx * kx + ky * ky + kz * kz <= g.k2max;
+  return std::llabs(kx) <= g.kmax && std::llabs(ky) <= g.kmax && kz <= g.kmax;
+}
+
+int kval_host(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+int isqrt_host(long long v) {
+  if (v < 0) return -1;
+  long long r = (long long)std::sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return (int)r;
+}
+
+int ybound_host(const Geom& g, int kz) {
+  if (g.mask == 0) return isqrt_host(g.k2max - (long long)kz * kz);
+  return kz <= g.kmax ? g.kmax : -1;
+}
+
+int num_shells(int n) {
+  const long long k2top = 3LL * (n / 2) * (n / 2);
+  const int r = isqrt_host(k2top);
+  const int s = ((long long)r * (r + 1) >= k2top) ? r : r + 1;
+  return s + 1;
+}
+
+const char* validate(const ns_config* c) {
+  if (c == nullptr) return "config is NULL";
+  if (!factor_ok(c->n, nullptr)) return "n must be 2^a 3^b 5^c with a >= 1 and 8 <= n <= 1024";
+  if (c->precision != NS_FP32 && c->precision != NS_FP64) return "precision must be NS_FP32 or NS_FP64";
+  if (c->mask != NS_MASK_SPHERE && c->mask != NS_MASK_CUBE) return "mask must be NS_MASK_SPHERE or NS_MASK_CUBE";
+  if (c->reserved != 0) return "reserved must be 0";
+  if (!(c->nu >= 0.0) || !std::isfinite(c->nu)) return "nu must be finite and >= 0";
+  if (!(c->ct > 0.0 && c->ct <= 1.0)) return "ct must satisfy 0 < ct <= 1";
+  const double kmax = c->ct * c->n / 2.0;
+  if (c->mask == NS_MASK_SPHERE ? largest_int_below(kmax * kmax) < 1 : largest_int_below(kmax) < 1)
+    return "ct too small: no non-zero mode is retained";
+  return nullptr;
+}
+
+bool make_layout(const ns_config* c, Layout* lay) {
+  std::vector<int> rad;
+  factor_ok(c->n, &rad);
+  Geom& g = lay->g;
+  const int n = c->n;
+  g.n = n;
+  g.h = n / 2 + 1;
+  g.mask = c->mask;
+  const double kmax = c->ct * n / 2.0;
+  if (c->mask == NS_MASK_SPHERE) {
+    g.k2max = largest_int_below(kmax * kmax);
+    g.kmax = isqrt_host(g.k2max);
+    lay->k2top = g.k2max;
+  } else {
+    g.kmax = (int)largest_int_below(kmax);
+    g.k2max = 3LL * g.kmax * g.kmax;
+    lay->k2top = g.k2max;
+  }
+  g.kzn = g.kmax + 1;
+  lay->elem = c->precision == NS_FP32 ? 8 : 16;
+  int L = c->precision == NS_FP32 ? 16 : 8;
+  int tx = 0;
+  for (;;) {
+    tx = (n * L + kEpt - 1) / kEpt;
+    tx = (tx + 63) / 64 * 64;
+    if (tx <= 512 || L == 1) break;
+    L /= 2;
+  }
+  g.L = L;
+  g.lgL = 0;
+  while ((1 << g.lgL) < L) ++g.lgL;
+  lay->tx = tx;
+  g.kzp = (g.kzn + L - 1) / L * L;
+  g.comp = (long long)n * n * g.h;
+  g.wcomp = (long long)n * n * g.kzp;
+  lay->ntz = (g.kzn + L - 1) / L;
+  lay->ntzf = (g.h + L - 1) / L;
+  // z pass: P lines per block, P a power of two dividing n^2, 3 P n <= kEptZ * tz
+  int pz = 2;
+  while (3 * (2 * pz) * n <= kEptZ * 256 && ((long long)n * n) % (2 * pz) == 0 && 2 * pz <= 32) pz *= 2;
+  int tz = 256;
+  while (3 * pz * n > kEptZ * tz) tz *= 2;
+  lay->pz = pz;
+  lay->tz = tz;
+  // plan
+  FftPlan& p = lay->plan;
+  std::memset(&p, 0, sizeof(p));
+  p.n = n;
+  p.nstages = (int)rad.size();
+  int ns = 1;
+  for (int s = 0; s < p.nstages; ++s) {
+    p.radix[s] = rad[s];
+    p.ns[s] = ns;
+    p.tstride[s] = n / (ns * rad[s]);
+    ns *= rad[s];
+  }
+  // active (k_y, k_z tile) lines of the x passes
+  lay->tiles.clear();
+  for (int yi = 0; yi < n; ++yi) {
+    const int ky = kval_host(yi, n);
+    for (int t = 0; t < lay->ntz; ++t) {
+      const int kz0 = t * L;
+      if (kz0 < g.kzn && std::abs(ky) <= ybound_host(g, kz0)) lay->tiles.push_back(make_int2(yi, kz0));
+    }
+  }
+  lay->nsh = num_shells(n);
+  lay->nbins = 3 * lay->nsh + 3 * g.h + 5;
+  // workspace
+  const size_t e = lay->elem, rsz = e / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, kAlign); return o; };
+  lay->off_tw = take(n * e);
+  lay->off_ph = take((2 * n + g.h) * e);
+  lay->off_etab = take(2 * (size_t)(lay->k2top + 1) * rsz);
+  lay->off_force = take(3 * 196 * e);
+  lay->off_tiles = take(lay->tiles.size() * sizeof(int2) + 8);
+  lay->off_w = take(6 * (size_t)g.wcomp * e);
+  lay->off_s = take(3 * (size_t)g.comp * e);
+  lay->off_a = take(3 * (size_t)g.comp * e);
+  lay->off_spec = take((size_t)kSpecBlocks * lay->nbins * sizeof(double));
+  lay->off_specout = take((size_t)lay->nbins * sizeof(double));
+  lay->total = off;
+  return true;
+}
+
+}  // namespace
+
+struct ns_ctx {
+  ns_config cfg;
+  hipStream_t stream;
+  Layout lay;
+  char* ws;
+  std::string err;
+  std::vector<double> host_spec;
+};
+
+namespace {
+
+ns_status fail(ns_ctx* c, ns_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_last_error = msg;
+  return s;
+}
+
+ns_status hip_check(ns_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return NS_OK;
+  return fail(c, NS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+template <typename R>
+struct Ptrs {
+  Cx<R>* tw;
+  Cx<R>* ph;
+  R* eh;
+  R* edt;
+  Cx<R>* force;
+  int2* tiles;
+  Cx<R>* W;
+  Cx<R>* sb;
+  Cx<R>* ab;
+  double* spec;
+  double* specout;
+};
+
+template <typename R>
+Ptrs<R> ptrs(ns_ctx* c) {
+  const Layout& l = c->lay;
+  Ptrs<R> p;
+  p.tw = reinterpret_cast<Cx<R>*>(c->ws + l.off_tw);
+  p.ph = reinterpret_cast<Cx<R>*>(c->ws + l.off_ph);
+  p.eh = reinterpret_cast<R*>(c->ws + l.off_etab);
+  p.edt = p.eh + (l.k2top + 1);
+  p.force = reinterpret_cast<Cx<R>*>(c->ws + l.off_force);
+  p.tiles = reinterpret_cast<int2*>(c->ws + l.off_tiles);
+  p.W = reinterpret_cast<Cx<R>*>(c->ws + l.off_w);
+  p.sb = reinterpret_cast<Cx<R>*>(c->ws + l.off_s);
+  p.ab = reinterpret_cast<Cx<R>*>(c->ws + l.off_a);
+  p.spec = reinterpret_cast<double*>(c->ws + l.off_spec);
+  p.specout = reinterpret_cast<double*>(c->ws + l.off_specout);
+  return p;
+}
+
+size_t lds_strided(const Layout& l) { return (size_t)(l.g.n + l.g.n * l.g.L) * l.elem; }
+size_t lds_z(const Layout& l) { return (size_t)(l.g.n + 3 * l.pz * l.g.n) * l.elem; }
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename R, int OP>
+hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, int shifted, const EpiArgs<R>& a) {
+  const Layout& l = c->lay;
+  const size_t lds = lds_strided(l);
+  auto kern = ns::k_xfwd<R, kEpt, OP>;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int nblk = a.full ? l.g.n * l.ntzf : (int)l.tiles.size();
+  if (nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, p.ph, shifted,
+                     p.tiles, l.g, l.plan, a);
+  return hipGetLastError();
+}
+
+// One evaluation of the nonlinear term on the state-layout array `in` with the
+// shift s (NULL or all zero = unshifted); the x-forward epilogue applies OP.
+template <typename R, int OP>
+ns_status eval(ns_ctx* c, const Cx<R>* in, const double* s, EpiArgs<R> a) {
+  const Layout& l = c->lay;
+  const Geom& g = l.g;
+  Ptrs<R> p = ptrs<R>(c);
+  const int shifted = (s != nullptr && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0)) ? 1 : 0;
+  hipError_t e;
+  if (shifted) {
+    const int nt = 2 * g.n + g.h;
+    hipLaunchKernelGGL(ns::k_phase<R>, dim3((nt + 255) / 256), dim3(256), 0, c->stream, p.ph, g.n,
+                       g.h, s[0], s[1], s[2]);
+  }
+  const size_t lds = lds_strided(l);
+  const int ntiles = (int)l.tiles.size();
+  if (ntiles > 0) {
+    auto k1 = ns::k_xinv<R, kEpt>;
+    if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
+    hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, in, p.W, p.tw, p.ph, shifted,
+                       p.tiles, g, l.plan);
+    auto k2 = ns::k_ypass<R, kEpt, +1>;
+    if ((e = allow_lds(k2, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
+    hipLaunchKernelGGL(k2, dim3(6 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
+                       l.plan);
+    const size_t ldsz = lds_z(l);
+    auto k3 = ns::k_zcross<R, kEptZ>;
+    if ((e = allow_lds(k3, ldsz)) != hipSuccess) return hip_check(c, e, "k_zcross attribute");
+    hipLaunchKernelGGL(k3, dim3((int)((long long)g.n * g.n / l.pz)), dim3(l.tz), ldsz, c->stream,
+                       p.W, p.tw, l.pz, g, l.plan);
+    auto k4 = ns::k_ypass<R, kEpt, -1>;
+    if ((e = allow_lds(k4, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
+    hipLaunchKernelGGL(k4, dim3(3 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
+                       l.plan);
+  }
+  if ((e = launch_xfwd<R, OP>(c, p, shifted, a)) != hipSuccess) return hip_check(c, e, "k_xfwd launch");
+  return hip_check(c, hipGetLastError(), "nonlinear-term launch");
+}
+
+template <typename R>
+EpiArgs<R> epi(ns_ctx* c, int full) {
+  EpiArgs<R> a;
+  std::memset(&a, 0, sizeof(a));
+  Ptrs<R> p = ptrs<R>(c);
+  a.eh = p.eh;
+  a.edt = p.edt;
+  a.full = full;
+  a.ntzf = c->lay.ntzf;
+  return a;
+}
+
+template <typename R>
+ns_status nonlinear_t(ns_ctx* c, const void* u, void* nh, const double* shift, int flags) {
+  const Cx<R>* in = static_cast<const Cx<R>*>(u);
+  Cx<R>* out = static_cast<Cx<R>*>(nh);
+  EpiArgs<R> a = epi<R>(c, 1);
+  a.out0 = out;
+  if (flags & NS_NL_PS_AVG) {
+    const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
+    ns_status st = eval<R, ns::OP_STORE>(c, in, zero, a);
+    if (st != NS_OK) return st;
+    a.in1 = out;
+    return eval<R, ns::OP_AVG>(c, in, half, a);
+  }
+  return eval<R, ns::OP_STORE>(c, in, shift, a);
+}
+
+template <typename R>
+ns_status etab(ns_ctx* c, double dt) {
+  Ptrs<R> p = ptrs<R>(c);
+  const long long nt = c->lay.k2top + 1;
+  hipLaunchKernelGGL(ns::k_etab<R>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, p.eh,
+                     p.edt, c->lay.k2top, c->cfg.nu, dt);
+  return hip_check(c, hipGetLastError(), "k_etab launch");
+}
+
+template <typename R>
+ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
+  Cx<R>* s0 = static_cast<Cx<R>*>(u);
+  Ptrs<R> p = ptrs<R>(c);
+  ns_status st = etab<R>(c, dt);
+  if (st != NS_OK) return st;
+  for (int i = 0; i < nsteps; ++i) {
+    EpiArgs<R> a = epi<R>(c, 0);
+    a.dt = R(dt);
+    a.in0 = s0;
+    a.in1 = p.ab;
+    a.out0 = p.ab;
+    a.out1 = p.sb;
+    if ((st = eval<R, ns::OP_RK4_0>(c, s0, nullptr, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_RK4_1>(c, p.sb, nullptr, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_RK4_2>(c, p.sb, nullptr, a)) != NS_OK) return st;
+    EpiArgs<R> f = epi<R>(c, 1);
+    f.dt = R(dt);
+    f.in1 = p.ab;
+    f.out0 = s0;
+    if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, nullptr, f)) != NS_OK) return st;
+  }
+  return NS_OK;
+}
+
+uint64_t sm64_mix_host(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double sm64_uniform_host(uint64_t seed, long long step, long long j) {
+  const uint64_t G = 0x9E3779B97F4A7C15ull;
+  const uint64_t s = sm64_mix_host(seed + G * (uint64_t)(step + 1));
+  return (double)(sm64_mix_host(s + G * (uint64_t)(j + 1)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename R>
+ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const double* alphas,
+               const ns_forcing* fo, long long step0) {
+  Cx<R>* s0 = static_cast<Cx<R>*>(u);
+  Ptrs<R> p = ptrs<R>(c);
+  ns_status st = etab<R>(c, dt);
+  if (st != NS_OK) return st;
+  const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
+  for (int i = 0; i < nsteps; ++i) {
+    if (variant == NS_PS_EXACT) {
+      EpiArgs<R> a = epi<R>(c, 0);
+      a.dt = R(dt);
+      a.out0 = p.ab;
+      if ((st = eval<R, ns::OP_STORE>(c, s0, zero, a)) != NS_OK) return st;
+      a.in0 = s0;
+      a.in1 = p.ab;
+      a.out0 = p.sb;
+      if ((st = eval<R, ns::OP_EX1B>(c, s0, half, a)) != NS_OK) return st;
+      a.out0 = p.ab;
+      if ((st = eval<R, ns::OP_STORE>(c, p.sb, zero, a)) != NS_OK) return st;
+      EpiArgs<R> f = epi<R>(c, 1);
+      f.dt = R(dt);
+      f.in0 = s0;
+      f.in1 = p.ab;
+      f.out0 = s0;
+      if ((st = eval<R, ns::OP_EX2B>(c, p.sb, half, f)) != NS_OK) return st;
+      continue;
+    }
+    double al[3] = {0, 0, 0};
+    if (variant == NS_PS_RANDOM) {
+      for (int j = 0; j < 3; ++j)
+        al[j] = alphas ? alphas[3 * i + j] : sm64_uniform_host(c->cfg.seed, step0 + i, j);
+    }
+    double be[3];
+    for (int j = 0; j < 3; ++j) be[j] = std::fmod(al[j] + 0.5, 1.0);
+    EpiArgs<R> a = epi<R>(c, 0);
+    a.dt = R(dt);
+    a.in0 = s0;
+    a.out0 = p.ab;
+    a.out1 = p.sb;
+    if (fo != nullptr) {
+      const Geom& g = c->lay.g;
+      hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(64), 0, c->stream, s0, p.force, g.n, g.h,
+                         g.comp, fo->seed, step0 + i, dt, fo->injection);
+      if ((st = hip_check(c, hipGetLastError(), "k_forcing launch")) != NS_OK) return st;
+      a.force = p.force;
+    }
+    if ((st = eval<R, ns::OP_HEUN1>(c, s0, al, a)) != NS_OK) return st;
+    EpiArgs<R> f = epi<R>(c, 1);
+    f.dt = R(dt);
+    f.in1 = p.ab;
+    f.out0 = s0;
+    if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, be, f)) != NS_OK) return st;
+  }
+  return NS_OK;
+}
+
+template <typename R>
+ns_status spectra_t(ns_ctx* c, const void* u, const void* nh, ns_spectra_out* out) {
+  const Layout& l = c->lay;
+  Ptrs<R> p = ptrs<R>(c);
+  const size_t lds = (size_t)l.nbins * sizeof(double);
+  hipError_t e = allow_lds(ns::k_spectra<R>, lds);
+  if (e != hipSuccess) return hip_check(c, e, "k_spectra attribute");
+  hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(256), lds, c->stream,
+                     static_cast<const Cx<R>*>(u), static_cast<const Cx<R>*>(nh), c->cfg.nu, l.g.n,
+                     l.g.h, l.nsh, l.g.comp, p.spec);
+  hipLaunchKernelGGL(ns::k_spectra_sum, dim3((l.nbins + 255) / 256), dim3(256), 0, c->stream, p.spec,
+                     kSpecBlocks, l.nbins, p.specout);
+  ns_status st = hip_check(c, hipGetLastError(), "spectra launch");
+  if (st != NS_OK) return st;
+  c->host_spec.resize(l.nbins);
+  st = hip_check(c, hipMemcpyAsync(c->host_spec.data(), p.specout, l.nbins * sizeof(double),
+                                   hipMemcpyDeviceToHost, c->stream), "spectra copy");
+  if (st != NS_OK) return st;
+  st = hip_check(c, hipStreamSynchronize(c->stream), "spectra synchronize");
+  if (st != NS_OK) return st;
+  const double* b = c->host_spec.data();
+  const int nsh = l.nsh, h = l.g.h;
+  if (out->e_shell) std::memcpy(out->e_shell, b, nsh * sizeof(double));
+  if (out->d_shell) std::memcpy(out->d_shell, b + nsh, nsh * sizeof(double));
+  if (out->t_shell) std::memcpy(out->t_shell, b + 2 * nsh, nsh * sizeof(double));
+  if (out->e_1d) std::memcpy(out->e_1d, b + 3 * nsh, 3 * h * sizeof(double));
+  if (out->totals) std::memcpy(out->totals, b + 3 * nsh + 3 * h, 5 * sizeof(double));
+  if (b[3 * nsh + 3 * h + 4] != 0.0) return fail(c, NS_ERR_NONFINITE, "non-finite entries in input");
+  return NS_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+size_t ns_workspace_bytes(const ns_config* cfg) {
+  const char* m = validate(cfg);
+  if (m) { g_last_error = m; return 0; }
+  Layout lay;
+  make_layout(cfg, &lay);
+  return lay.total;
+}
+
+int32_t ns_num_shells(int32_t n) { return n >= 2 ? num_shells(n) : 0; }
+
+int64_t ns_retained_bound(const ns_config* cfg) {
+  const char* m = validate(cfg);
+  if (m) { g_last_error = m; return -1; }
+  Layout lay;
+  make_layout(cfg, &lay);
+  return cfg->mask == NS_MASK_SPHERE ? lay.g.k2max : lay.g.kmax;
+}
+
+ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx** out) {
+  if (out == nullptr) return fail(nullptr, NS_ERR_ARG, "out is NULL");
+  const char* m = validate(cfg);
+  if (m) return fail(nullptr, NS_ERR_ARG, m);
+  if (!aligned(workspace)) return fail(nullptr, NS_ERR_ARG, "workspace must be a non-NULL 256-byte aligned device pointer");
+  ns_ctx* c = new (std::nothrow) ns_ctx;
+  if (!c) return fail(nullptr, NS_ERR_STATE, "out of host memory");
+  c->cfg = *cfg;
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  make_layout(cfg, &c->lay);
+  if (ws_bytes < c->lay.total) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "workspace too small: %zu bytes given, %zu needed", ws_bytes, c->lay.total);
+    delete c;
+    return fail(nullptr, NS_ERR_SIZE, msg);
+  }
+  c->ws = static_cast<char*>(workspace);
+  // twiddles W_N^t = exp(-2 pi i t/N), long double, rounded once
+  const int n = cfg->n;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<char> tw(n * c->lay.elem);
+  for (int t = 0; t < n; ++t) {
+    const long double a = -2.0L * pi * (long double)t / (long double)n;
+    const long double cs = std::cos(a), sn = std::sin(a);
+    if (cfg->precision == NS_FP32) {
+      float v[2] = {(float)cs, (float)sn};
+      std::memcpy(tw.data() + t * 8, v, 8);
+    } else {
+      double v[2] = {(double)cs, (double)sn};
+      std::memcpy(tw.data() + t * 16, v, 16);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(c->ws + c->lay.off_tw, tw.data(), tw.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && !c->lay.tiles.empty())
+    e = hipMemcpyAsync(c->ws + c->lay.off_tiles, c->lay.tiles.data(), c->lay.tiles.size() * sizeof(int2),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    std::string msg = std::string("upload of tables failed: ") + hipGetErrorString(e);
+    delete c;
+    return fail(nullptr, NS_ERR_HIP, msg);
+  }
+  *out = c;
+  return NS_OK;
+}
+
+ns_status ns_destroy(ns_ctx* ctx) {
+  delete ctx;
+  return NS_OK;
+}
+
+const char* ns_last_error(const ns_ctx* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+ns_status ns_set_stream(ns_ctx* ctx, void* stream) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->cfg.stream = stream;
+  return NS_OK;
+}
+
+ns_status ns_nonlinear(ns_ctx* ctx, const void* u_hat, void* n_hat, const double shift[3], int32_t flags) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!aligned(u_hat) || !aligned(n_hat)) return fail(ctx, NS_ERR_ARG, "u_hat and n_hat must be non-NULL 256-byte aligned device pointers");
+  if (u_hat == n_hat) return fail(ctx, NS_ERR_ARG, "u_hat and n_hat must not overlap");
+  if (flags & ~NS_NL_PS_AVG) return fail(ctx, NS_ERR_ARG, "unknown flags");
+  if (shift && !(std::isfinite(shift[0]) && std::isfinite(shift[1]) && std::isfinite(shift[2])))
+    return fail(ctx, NS_ERR_ARG, "shift must be finite");
+  return ctx->cfg.precision == NS_FP32 ? nonlinear_t<float>(ctx, u_hat, n_hat, shift, flags)
+                                       : nonlinear_t<double>(ctx, u_hat, n_hat, shift, flags);
+}
+
+ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!aligned(u_hat)) return fail(ctx, NS_ERR_ARG, "u_hat must be a non-NULL 256-byte aligned device pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(ctx, NS_ERR_ARG, "nsteps must be >= 0");
+  if (nsteps == 0) return NS_OK;
+  return ctx->cfg.precision == NS_FP32 ? rk4_t<float>(ctx, u_hat, dt, nsteps)
+                                       : rk4_t<double>(ctx, u_hat, dt, nsteps);
+}
+
+ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps, int32_t variant,
+                                 const double* alphas, const ns_forcing* forcing, int64_t step0) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!aligned(u_hat)) return fail(ctx, NS_ERR_ARG, "u_hat must be a non-NULL 256-byte aligned device pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(ctx, NS_ERR_ARG, "nsteps must be >= 0");
+  if (variant != NS_PS_EXACT && variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
+    return fail(ctx, NS_ERR_ARG, "unknown phase-shift variant");
+  if (forcing) {
+    if (variant == NS_PS_EXACT) return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
+    if (forcing->k2_lo != 4 || forcing->k2_hi != 9) return fail(ctx, NS_ERR_ARG, "forcing shell must be 4 <= |k|^2 <= 9");
+    if (!(forcing->injection > 0.0) || !std::isfinite(forcing->injection)) return fail(ctx, NS_ERR_ARG, "injection must be finite and > 0");
+    const Geom& g = ctx->lay.g;
+    if (g.mask == 0 ? g.k2max < 9 : g.kmax < 3) return fail(ctx, NS_ERR_ARG, "forcing shell lies outside the retained set");
+  }
+  if (alphas && variant == NS_PS_RANDOM)
+    for (int i = 0; i < 3 * nsteps; ++i)
+      if (!std::isfinite(alphas[i])) return fail(ctx, NS_ERR_ARG, "alphas must be finite");
+  if (nsteps == 0) return NS_OK;
+  return ctx->cfg.precision == NS_FP32
+             ? ps_t<float>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0)
+             : ps_t<double>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0);
+}
+
+ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!out) return fail(ctx, NS_ERR_ARG, "out is NULL");
+  if (!aligned(u_hat) || (n_hat != nullptr && !aligned(n_hat)))
+    return fail(ctx, NS_ERR_ARG, "u_hat (and n_hat if given) must be 256-byte aligned device pointers");
+  return ctx->cfg.precision == NS_FP32 ? spectra_t<float>(ctx, u_hat, n_hat, out)
+                                       : spectra_t<double>(ctx, u_hat, n_hat, out);
+}
+
+ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt, int32_t variant,
+                                const double alpha[3]) {
+  (void)u_hat0; (void)lam; (void)dt; (void)variant; (void)alpha;
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  return fail(ctx, NS_ERR_STATE, "ns_vjp_rk2_phaseshift: not built in this library version");
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+"""Thin ctypes binding of libns.so (include/ns.h); argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  PyTorch provides device
+memory (the caller's field tensors and the workspace) and the stream.  If the
+library is missing the binding raises; there is no fallback.
+
+Field tensors: complex64 (FP32 contexts) or complex128 (FP64 contexts), shape
+[3, N, N, N//2+1], contiguous, on the context's device; layout and conventions
+as documented in include/ns.h.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libns.so")
+
+NS_OK, NS_ERR_ARG, NS_ERR_SIZE, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(6)
+NS_FP32, NS_FP64 = 0, 1
+NS_MASK_SPHERE, NS_MASK_CUBE = 0, 1
+NS_PS_EXACT, NS_PS_APPROX, NS_PS_RANDOM = 0, 1, 2
+NS_NL_PS_AVG = 1
+VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM}
+
+# every function declared in include/ns.h
+ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns_init", "ns_destroy",
+                 "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
+                 "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift")
+
+
+class NSConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("precision", ctypes.c_int32), ("mask", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("nu", ctypes.c_double), ("ct", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
+
+
+class NSForcing(ctypes.Structure):
+    _fields_ = [("k2_lo", ctypes.c_int32), ("k2_hi", ctypes.c_int32), ("injection", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class NSSpectraOut(ctypes.Structure):
+    _fields_ = [("e_shell", ctypes.c_void_p), ("d_shell", ctypes.c_void_p), ("t_shell", ctypes.c_void_p),
+                ("e_1d", ctypes.c_void_p), ("totals", ctypes.c_void_p)]
+
+
+class NSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libns status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libns.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_08892_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    cfgp = ctypes.POINTER(NSConfig)
+    sig = {
+        "ns_workspace_bytes": (S, [cfgp]),
+        "ns_num_shells": (I32, [I32]),
+        "ns_retained_bound": (I64, [cfgp]),
+        "ns_init": (I32, [cfgp, P, S, ctypes.POINTER(P)]),
+        "ns_destroy": (I32, [P]),
+        "ns_last_error": (ctypes.c_char_p, [P]),
+        "ns_set_stream": (I32, [P, P]),
+        "ns_nonlinear": (I32, [P, P, P, P, I32]),
+        "ns_step_rk4_trunc": (I32, [P, P, D, I32]),
+        "ns_step_rk2_phaseshift": (I32, [P, P, D, I32, I32, P, ctypes.POINTER(NSForcing), I64]),
+        "ns_spectra": (I32, [P, P, P, ctypes.POINTER(NSSpectraOut)]),
+        "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def make_config(n, nu, ct, mask="sphere", precision="fp32", seed=0, stream=None):
+    return NSConfig(int(n), NS_FP32 if precision == "fp32" else NS_FP64,
+                    NS_MASK_SPHERE if mask == "sphere" else NS_MASK_CUBE, 0, float(nu), float(ct),
+                    int(seed), stream)
+
+
+def workspace_bytes(n, nu, ct, mask="sphere", precision="fp32"):
+    return int(lib().ns_workspace_bytes(ctypes.byref(make_config(n, nu, ct, mask, precision))))
+
+
+def retained_bound(n, ct, mask="sphere"):
+    return int(lib().ns_retained_bound(ctypes.byref(make_config(n, 0.0, ct, mask))))
+
+
+def num_shells(n):
+    return int(lib().ns_num_shells(int(n)))
+
+
+def _dbl3(v):
+    if v is None:
+        return None
+    a = (ctypes.c_double * 3)(*[float(x) for x in v])
+    return a
+
+
+class Solver:
+    """One library context on a CUDA (HIP) device with its workspace tensor."""
+
+    def __init__(self, n, nu, ct, mask="sphere", precision="fp32", seed=0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.n, self.nu, self.ct, self.mask, self.precision = n, nu, ct, mask, precision
+        self.device = torch.device(device)
+        self.dtype = torch.complex64 if precision == "fp32" else torch.complex128
+        self.stream = torch.cuda.current_stream(self.device)
+        cfg = make_config(n, nu, ct, mask, precision, seed, ctypes.c_void_p(self.stream.cuda_stream))
+        L = lib()
+        nbytes = L.ns_workspace_bytes(ctypes.byref(cfg))
+        if nbytes == 0:
+            raise NSError(NS_ERR_ARG, L.ns_last_error(None).decode())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        ctx = ctypes.c_void_p()
+        st = L.ns_init(ctypes.byref(cfg), ctypes.c_void_p(base + off), nbytes, ctypes.byref(ctx))
+        if st != NS_OK:
+            raise NSError(st, L.ns_last_error(None).decode())
+        self.ctx = ctx
+        self.nshells = int(L.ns_num_shells(n))
+        self.bound = int(L.ns_retained_bound(ctypes.byref(cfg)))
+
+    def __del__(self):
+        if getattr(self, "ctx", None) is not None and _lib is not None:
+            _lib.ns_destroy(self.ctx)
+            self.ctx = None
+
+    def _check(self, st):
+        if st != NS_OK:
+            raise NSError(st, lib().ns_last_error(self.ctx).decode())
+
+    def _field(self, t, name):
+        shape = (3, self.n, self.n, self.n // 2 + 1)
+        if t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {shape} on {self.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _sync_stream(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream = cur
+            self._check(lib().ns_set_stream(self.ctx, ctypes.c_void_p(cur.cuda_stream)))
+
+    def empty(self):
+        return self.torch.zeros((3, self.n, self.n, self.n // 2 + 1), dtype=self.dtype, device=self.device)
+
+    def to_device(self, a):
+        """Copy a host complex array [3, N, N, N/2+1] into a new field tensor."""
+        t = self.torch.from_numpy(np.ascontiguousarray(a).astype(
+            np.complex64 if self.precision == "fp32" else np.complex128))
+        return t.to(self.device)
+
+    def nonlinear(self, u, out=None, shift=None, ps_avg=False):
+        self._sync_stream()
+        out = self.empty() if out is None else out
+        self._check(lib().ns_nonlinear(self.ctx, self._field(u, "u"), self._field(out, "out"),
+                                       _dbl3(shift), NS_NL_PS_AVG if ps_avg else 0))
+        return out
+
+    def step_rk4(self, u, dt, nsteps=1):
+        self._sync_stream()
+        self._check(lib().ns_step_rk4_trunc(self.ctx, self._field(u, "u"), float(dt), int(nsteps)))
+        return u
+
+    def step_ps(self, u, dt, nsteps=1, variant="random", alphas=None, forcing=None, step0=0):
+        """Phase-shift RK2 steps in place.  alphas: array [nsteps, 3] (random variant) or None;
+        forcing: dict(seed=..., injection=1.0) or None."""
+        self._sync_stream()
+        ap = None
+        if alphas is not None:
+            a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).reshape(-1))
+            if a.size != 3 * int(nsteps):
+                raise ValueError("alphas must have shape [nsteps, 3]")
+            ap = a.ctypes.data_as(ctypes.c_void_p)
+        fo = None
+        if forcing is not None:
+            fo = ctypes.byref(NSForcing(4, 9, float(forcing.get("injection", 1.0)), int(forcing["seed"])))
+        self._check(lib().ns_step_rk2_phaseshift(self.ctx, self._field(u, "u"), float(dt), int(nsteps),
+                                                 VARIANTS[variant], ap, fo, int(step0)))
+        return u
+
+    def spectra(self, u, n_hat=None, check_finite=True):
+        self._sync_stream()
+        nsh, h = self.nshells, self.n // 2 + 1
+        out = {"e_shell": np.zeros(nsh), "d_shell": np.zeros(nsh), "t_shell": np.zeros(nsh),
+               "e_1d": np.zeros((3, h)), "totals": np.zeros(5)}
+        so = NSSpectraOut(*[out[k].ctypes.data_as(ctypes.c_void_p) for k in
+                            ("e_shell", "d_shell", "t_shell", "e_1d", "totals")])
+        st = lib().ns_spectra(self.ctx, self._field(u, "u"),
+                              None if n_hat is None else self._field(n_hat, "n_hat"), ctypes.byref(so))
+        if st == NS_ERR_NONFINITE and not check_finite:
+            return out
+        self._check(st)
+        return out
+
+    def vjp_ps(self, u0, lam, dt, variant="random", alpha=None):
+        """In place: lam <- (dS_new/dS_0)^T lam for one unforced phase-shift RK2 step at u0."""
+        self._sync_stream()
+        self._check(lib().ns_vjp_rk2_phaseshift(self.ctx, self._field(u0, "u0"), self._field(lam, "lam"),
+                                                float(dt), VARIANTS[variant], _dbl3(alpha)))
+        return lam

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same
+seeded inputs.
+
+Tolerances: FP64 instantiation 1e-12 (relative L2 and relative to the largest
+entry).  FP32 fields: 1e-5 relative L2 per evaluation or per step (the stated
+FP32 field tolerance; FP32 round-off of ~log2(N^3) butterfly stages and one
+product gives ~1e-6 here), and 1e-4 relative to the largest entry: the
+projection removes the gradient part of u x omega, which on some high-|k|
+modes is one to two orders of magnitude larger than the solenoidal remainder,
+so the per-mode FP32 error is amplified there by |FFT(u x omega)| / |N|.
+The FP64 reference is computed from the same FP32-representable input.  FP64
+spectra: 1e-10 per bin (bins above 1e-30 of the total).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import forcing as oforcing
+from oracle import grid, schemes, spectra
+from oracle import nonlinear as onl
+from paper_2603_08892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4)}
+
+
+def _solver(n, ct, mask="sphere", prec="fp32", nu=0.01, seed=0):
+    from paper_2603_08892_amd import ns
+    return ns.Solver(n, nu, ct, mask=mask, precision=prec, seed=seed)
+
+
+def _rep(a, prec):
+    """The input as the device holds it (FP32 rounding for fp32), in complex128."""
+    return a.astype(np.complex64).astype(np.complex128) if prec == "fp32" else a.astype(np.complex128)
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _check(got, want, prec, what=""):
+    l2 = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    mx = np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
+    tl2, tmx = TOL[prec]
+    assert l2 <= tl2 and mx <= tmx, f"{what}: rel L2 {l2:.3e} rel max {mx:.3e}"
+
+
+def _field(n, ct, mask, seed, energy=None):
+    k2 = grid.sphere_k2max(n, ct) if mask == "sphere" else 3 * grid.cube_kmax(n, ct) ** 2
+    u = inputs.random_solenoidal(n, seed, k2, energy=energy)
+    return u * grid.mask(n, ct, mask)
+
+
+NL_CASES = [
+    (8, 1.0, "sphere", "fp64"), (12, 1.0, "sphere", "fp64"), (16, 2 / 3, "sphere", "fp64"),
+    (24, 1.0, "cube", "fp64"), (32, 2 / 3, "sphere", "fp64"), (40, 0.9, "sphere", "fp64"),
+    (48, 1.0, "sphere", "fp32"), (32, 1.0, "sphere", "fp32"), (60, 2 / 3, "cube", "fp32"),
+    (64, 1.0, "sphere", "fp32"), (96, 2 / 3, "sphere", "fp32"), (128, 1.0, "sphere", "fp32"),
+]
+
+
+@pytest.mark.parametrize("n,ct,mask,prec", NL_CASES)
+def test_nonlinear_parity(n, ct, mask, prec):
+    """ns_nonlinear for unshifted, half-cell, random shifts and the two-shift average."""
+    print(f"[nonlinear] n={n} ct={ct:.4f} mask={mask} prec={prec}", flush=True)
+    s = _solver(n, ct, mask, prec)
+    m = grid.mask(n, ct, mask)
+    u = _rep(_field(n, ct, mask, 1000 + n), prec)
+    ud = s.to_device(u)
+    for shift in [None, (0.5, 0.5, 0.5), (0.137, 0.71, 0.402)]:
+        got = _host(s.nonlinear(ud, shift=shift))
+        _check(got, onl.nonlinear(u, m, shift), prec, f"shift {shift}")
+    got = _host(s.nonlinear(ud, ps_avg=True))
+    _check(got, onl.nonlinear_ps(u, m), prec, "ps_avg")
+
+
+def test_nonlinear_ignores_modes_outside_mask():
+    """Entries outside the retained set are ignored on input and zero on output."""
+    n, ct = 32, 2 / 3
+    s = _solver(n, ct, "sphere", "fp64")
+    m = grid.mask(n, ct)
+    u = inputs.random_solenoidal(n, 5, 3 * (n // 2) ** 2)      # fills every mode
+    got = _host(s.nonlinear(s.to_device(u)))
+    _check(got, onl.nonlinear(u, m), "fp64")
+    assert np.all(got[:, ~m] == 0)
+
+
+def test_nonlinear_deterministic():
+    n = 64
+    s = _solver(n, 1.0)
+    ud = s.to_device(_field(n, 1.0, "sphere", 3))
+    a = _host(s.nonlinear(ud, shift=(0.3, 0.2, 0.9)))
+    b = _host(s.nonlinear(ud, shift=(0.3, 0.2, 0.9)))
+    assert np.array_equal(a, b)
+
+
+def test_taylor_green_closed_form_on_gpu():
+    """The GPU nonlinear term of the Taylor-Green field (Eq. T-G-init) is the
+    hand-derived one: -(1/8)(sin2x cos2z, sin2y cos2z, -(cos2x+cos2y) sin2z)."""
+    n = 32
+    s = _solver(n, 2 / 3, prec="fp64")
+    got = _host(s.nonlinear(s.to_device(inputs.taylor_green(n))))
+    want = np.zeros_like(got)
+    for (kx, kz, val) in [(2, 2, 1j / 32), (-2, 2, -1j / 32)]:
+        want[0, kx % n, 0, kz] = val
+        want[1, 0, kx % n, kz] = val
+    for kx in (2, -2):
+        want[2, kx % n, 0, 2] = -1j / 32
+        want[2, 0, kx % n, 2] = -1j / 32
+    assert np.abs(got - want).max() < 1e-15
+
+
+def _oracle_step(model, u, dt, scheme, alpha=None, force=None):
+    if scheme == "rk4":
+        return schemes.rk4(model, u, dt)
+    if scheme == "exact":
+        return schemes.ps_exact(model, u, dt)
+    return schemes.ps_heun(model, u, dt, alpha, forcing=force)
+
+
+STEP_CASES = [(16, 1.0, "fp64"), (24, 2 / 3, "fp64"), (32, 1.0, "fp32"), (48, 0.9, "fp32"), (64, 2 / 3, "fp32")]
+
+
+@pytest.mark.parametrize("n,ct,prec", STEP_CASES)
+@pytest.mark.parametrize("scheme", ["rk4", "exact", "approx", "random"])
+def test_one_step_parity(n, ct, prec, scheme):
+    print(f"[step] n={n} ct={ct:.4f} prec={prec} scheme={scheme}", flush=True)
+    nu, dt = 0.02, 0.01
+    s = _solver(n, ct, prec=prec, nu=nu, seed=77)
+    m = grid.mask(n, ct)
+    model = onl.NSModel(n, nu, m)
+    u = _rep(_field(n, ct, "sphere", 2000 + n, energy=0.5), prec)
+    ud = s.to_device(u)
+    if scheme == "rk4":
+        s.step_rk4(ud, dt, 1)
+        want = _oracle_step(model, u, dt, "rk4")
+    elif scheme == "exact":
+        s.step_ps(ud, dt, 1, "exact")
+        want = _oracle_step(model, u, dt, "exact")
+    elif scheme == "approx":
+        s.step_ps(ud, dt, 1, "approx")
+        want = _oracle_step(model, u, dt, "heun", alpha=(0, 0, 0))
+    else:
+        s.step_ps(ud, dt, 1, "random", step0=5)            # alpha from SplitMix64(seed, 5)
+        want = _oracle_step(model, u, dt, "heun", alpha=oforcing.random_shift(77, 5))
+    got = _host(ud)
+    _check(got, want, prec, scheme)
+    if prec == "fp64":  # the increment S_new - E S0 itself, which carries the nonlinear term
+        lin = model.E(dt) * u
+        _check(got - lin, want - lin, prec, scheme + " increment")
+
+
+def test_random_shifts_given_explicitly():
+    n, ct, nu, dt = 24, 1.0, 0.02, 0.01
+    s = _solver(n, ct, prec="fp64", nu=nu)
+    m = grid.mask(n, ct)
+    model = onl.NSModel(n, nu, m)
+    u = _field(n, ct, "sphere", 9, energy=0.5)
+    al = inputs.random_shifts(4, 3)
+    ud = s.to_device(u)
+    s.step_ps(ud, dt, 3, "random", alphas=al)
+    want = u
+    for i in range(3):
+        want = schemes.ps_heun(model, want, dt, tuple(al[i]))
+    _check(_host(ud), want, "fp64", "random explicit")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_split_forcing_parity(prec):
+    """RK2 phase-shift random split with the shell forcing (Eq. forcing-eq)."""
+    n, ct, nu, dt = 32, 1.0, 0.01, 0.005
+    s = _solver(n, ct, prec=prec, nu=nu, seed=3)
+    m = grid.mask(n, ct)
+    model = onl.NSModel(n, nu, m)
+    u = _rep(inputs.hit_initial(n, 8, grid.sphere_k2max(n, ct)), prec)
+    ud = s.to_device(u)
+    s.step_ps(ud, dt, 2, "random", forcing={"seed": 11, "injection": 1.0}, step0=4)
+    want = u
+    for i in range(2):
+        o = oforcing.forcing(want, dt, 11, 4 + i)
+        want = schemes.ps_heun(model, want, dt, oforcing.random_shift(3, 4 + i), forcing=o)
+    _check(_host(ud), want, prec, "split forcing")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_taylor_green_config_small(prec):
+    """Taylor-Green, N = 32, nu = 1/1600, dt = 1e-3, 10 steps of RK4 (C_t = 2/3) and of
+    RK2 phase-shift exact (C_t = 1): the small Taylor-Green workload."""
+    n, nu, dt = 32, 1 / 1600, 1e-3
+    u0 = inputs.taylor_green(n)
+    for scheme, ct in (("rk4", 2 / 3), ("exact", 1.0)):
+        s = _solver(n, ct, prec=prec, nu=nu)
+        model = onl.NSModel(n, nu, grid.mask(n, ct))
+        ud = s.to_device(u0)
+        want = u0
+        for _ in range(10):
+            want = _oracle_step(model, want, dt, scheme)
+        if scheme == "rk4":
+            s.step_rk4(ud, dt, 10)
+        else:
+            s.step_ps(ud, dt, 10, "exact")
+        tol = 1e-12 if prec == "fp64" else 1e-5
+        got = _host(ud)
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < tol, scheme
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spectra_parity(prec):
+    n, ct, nu = 32, 1.0, 0.013
+    s = _solver(n, ct, prec=prec, nu=nu)
+    m = grid.mask(n, ct)
+    u = _rep(_field(n, ct, "sphere", 31, energy=0.7), prec)
+    ud = s.to_device(u)
+    nh = s.nonlinear(ud, ps_avg=True)
+    nh_h = _host(nh)
+    got = s.spectra(ud, nh)
+    want = spectra.spectra(u, nu, nh_h)
+    for key in ("e_shell", "d_shell", "t_shell", "e_1d"):
+        g, w = got[key], want[key]
+        big = np.abs(w) > 1e-30 * np.abs(w).sum()
+        assert np.all(np.abs(g[big] - w[big]) <= 1e-10 * np.abs(w[big]) + 1e-14 * np.abs(w).max()), key
+    gt, wt = got["totals"], want["totals"]
+    assert np.allclose(gt[:3], wt[:3], rtol=1e-10, atol=0)
+    assert abs(gt[3] - wt[3]) <= 1e-10 * np.sqrt(spectra.inner(u, u) * spectra.inner(nh_h, nh_h))
+    assert gt[4] == 0
+
+
+def test_spectra_flags_nonfinite():
+    from paper_2603_08892_amd import ns
+    n = 16
+    s = _solver(n, 1.0, prec="fp64")
+    u = _field(n, 1.0, "sphere", 1)
+    u[1, 2, 3, 1] = np.nan
+    with pytest.raises(ns.NSError) as e:
+        s.spectra(s.to_device(u))
+    assert e.value.status == ns.NS_ERR_NONFINITE
+    out = s.spectra(s.to_device(u), check_finite=False)
+    assert out["totals"][4] == 1
+
+
+def test_zero_steps_and_argument_errors():
+    from paper_2603_08892_amd import ns
+    n = 16
+    s = _solver(n, 1.0, prec="fp64")
+    u = _field(n, 1.0, "sphere", 2)
+    ud = s.to_device(u)
+    s.step_rk4(ud, 0.1, 0)
+    s.step_ps(ud, 0.1, 0, "random")
+    assert np.array_equal(_host(ud), u)
+    with pytest.raises(ns.NSError):
+        s.step_rk4(ud, -0.1, 1)
+    with pytest.raises(ns.NSError):
+        s.step_ps(ud, 0.1, 1, "exact", forcing={"seed": 1})
+    with pytest.raises(ns.NSError):
+        s.nonlinear(ud, out=ud)
+
+
+def test_energy_conservation_on_gpu():
+    """Sum w Re(conj(u).N) = 0 for every shift (u.(u x omega) = 0 on any grid)."""
+    n = 64
+    s = _solver(n, 1.0, prec="fp32")
+    u = _rep(_field(n, 1.0, "sphere", 12), "fp32")
+    ud = s.to_device(u)
+    for shift in [None, (0.5, 0.5, 0.5), (0.2, 0.6, 0.1)]:
+        nh = _host(s.nonlinear(ud, shift=shift))
+        scale = np.sqrt(spectra.inner(u, u) * spectra.inner(nh, nh))
+        assert abs(spectra.inner(u, nh)) <= 1e-6 * scale
