@@ -180,6 +180,19 @@ ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spect
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt,
                                 int32_t variant, const double alpha[3]);
 
+/* Per-pass timing, the GPU counterpart of the per-task time shares of the
+ * paper's profiles (Figs. 10 and 14).  While enabled, every launch of the five
+ * passes of a nonlinear-term evaluation is bracketed by HIP events recorded on
+ * the context's stream (this adds a little overhead per launch).  Passes:
+ * 0 x-inverse (shift, curl), 1 y-inverse, 2 fused z (c2r, u x omega, r2c),
+ * 3 y-forward, 4 x-forward (projection, mask, Runge-Kutta stage).
+ * ns_timing_read waits for the stream, writes per pass the summed event-to-event
+ * milliseconds and the number of launches since the previous read (host arrays
+ * of NS_NUM_PASSES entries; either may be NULL) and clears the record. */
+#define NS_NUM_PASSES 5
+ns_status ns_timing_enable(ns_ctx* ctx, int32_t enable);
+ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

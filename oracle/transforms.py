@@ -14,7 +14,19 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-WORKERS = os.cpu_count() or 1
+def _workers():
+    # threads this process may use: its CPU affinity, capped by OMP_NUM_THREADS when set
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+WORKERS = _workers()
 AXES = (-3, -2, -1)
 
 

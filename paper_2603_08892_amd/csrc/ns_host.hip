@@ -206,6 +206,14 @@ struct ns_ctx {
   char* ws;
   std::string err;
   std::vector<double> host_spec;
+  // per-pass timing: events[2 i], events[2 i + 1] bracket launch i of pass tpass[i]
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  std::vector<int> tpass;
+  size_t tused = 0;
+  ~ns_ctx() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -222,6 +230,29 @@ ns_status hip_check(ns_ctx* c, hipError_t e, const char* what) {
 }
 
 bool aligned(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+// Timing brackets around one pass launch (no-ops unless timing is enabled).
+hipError_t tstart(ns_ctx* c, int pass) {
+  if (!c->timing) return hipSuccess;
+  if (2 * c->tused + 2 > c->events.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      c->events.push_back(e);
+    }
+    c->tpass.push_back(pass);
+  }
+  c->tpass[c->tused] = pass;
+  return hipEventRecord(c->events[2 * c->tused], c->stream);
+}
+
+hipError_t tstop(ns_ctx* c) {
+  if (!c->timing) return hipSuccess;
+  hipError_t r = hipEventRecord(c->events[2 * c->tused + 1], c->stream);
+  ++c->tused;
+  return r;
+}
 
 template <typename R>
 struct Ptrs {
@@ -299,23 +330,33 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, const double* s, EpiArgs<R> a) {
   if (ntiles > 0) {
     auto k1 = ns::k_xinv<R, kEpt>;
     if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
+    if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, in, p.W, p.tw, p.ph, shifted,
                        p.tiles, g, l.plan);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     auto k2 = ns::k_ypass<R, kEpt, +1>;
     if ((e = allow_lds(k2, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
+    if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL(k2, dim3(6 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
                        l.plan);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     const size_t ldsz = lds_z(l);
     auto k3 = ns::k_zcross<R, kEptZ>;
     if ((e = allow_lds(k3, ldsz)) != hipSuccess) return hip_check(c, e, "k_zcross attribute");
+    if ((e = tstart(c, 2)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL(k3, dim3((int)((long long)g.n * g.n / l.pz)), dim3(l.tz), ldsz, c->stream,
                        p.W, p.tw, l.pz, g, l.plan);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     auto k4 = ns::k_ypass<R, kEpt, -1>;
     if ((e = allow_lds(k4, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
+    if ((e = tstart(c, 3)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL(k4, dim3(3 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
                        l.plan);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   }
+  if ((e = tstart(c, 4)) != hipSuccess) return hip_check(c, e, "timing event");
   if ((e = launch_xfwd<R, OP>(c, p, shifted, a)) != hipSuccess) return hip_check(c, e, "k_xfwd launch");
+  if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   return hip_check(c, hipGetLastError(), "nonlinear-term launch");
 }
 
@@ -616,6 +657,33 @@ ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spect
     return fail(ctx, NS_ERR_ARG, "u_hat (and n_hat if given) must be 256-byte aligned device pointers");
   return ctx->cfg.precision == NS_FP32 ? spectra_t<float>(ctx, u_hat, n_hat, out)
                                        : spectra_t<double>(ctx, u_hat, n_hat, out);
+}
+
+ns_status ns_timing_enable(ns_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return NS_OK;
+}
+
+ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  double acc[NS_NUM_PASSES] = {0};
+  int64_t cnt[NS_NUM_PASSES] = {0};
+  ns_status st = hip_check(ctx, hipStreamSynchronize(ctx->stream), "timing synchronize");
+  if (st != NS_OK) return st;
+  for (size_t i = 0; i < ctx->tused; ++i) {
+    float t = 0.f;
+    st = hip_check(ctx, hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]), "timing elapsed");
+    if (st != NS_OK) return st;
+    acc[ctx->tpass[i]] += t;
+    cnt[ctx->tpass[i]] += 1;
+  }
+  ctx->tused = 0;
+  for (int k = 0; k < NS_NUM_PASSES; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  return NS_OK;
 }
 
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt, int32_t variant,

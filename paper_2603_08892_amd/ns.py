@@ -27,7 +27,9 @@ VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM
 # every function declared in include/ns.h
 ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns_init", "ns_destroy",
                  "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
-                 "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift")
+                 "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift", "ns_timing_enable",
+                 "ns_timing_read")
+PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue")
 
 
 class NSConfig(ctypes.Structure):
@@ -78,6 +80,8 @@ def lib():
         "ns_step_rk2_phaseshift": (I32, [P, P, D, I32, I32, P, ctypes.POINTER(NSForcing), I64]),
         "ns_spectra": (I32, [P, P, P, ctypes.POINTER(NSSpectraOut)]),
         "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P]),
+        "ns_timing_enable": (I32, [P, I32]),
+        "ns_timing_read": (I32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -216,3 +220,15 @@ class Solver:
         self._check(lib().ns_vjp_rk2_phaseshift(self.ctx, self._field(u0, "u0"), self._field(lam, "lam"),
                                                 float(dt), VARIANTS[variant], _dbl3(alpha)))
         return lam
+
+    def timing(self, enable):
+        """Enable or disable per-pass event timing on this context."""
+        self._check(lib().ns_timing_enable(self.ctx, 1 if enable else 0))
+
+    def timing_read(self):
+        """Per-pass {name: (total ms, launches)} since the previous read (waits for the stream)."""
+        ms = np.zeros(len(PASS_NAMES))
+        cnt = np.zeros(len(PASS_NAMES), dtype=np.int64)
+        self._check(lib().ns_timing_read(self.ctx, ms.ctypes.data_as(ctypes.c_void_p),
+                                         cnt.ctypes.data_as(ctypes.c_void_p)))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(PASS_NAMES)}
