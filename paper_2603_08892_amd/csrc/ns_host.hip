@@ -14,12 +14,15 @@
 #include <vector>
 
 #include "../../include/ns.h"
+#include "ns_adjoint.hpp"
 #include "ns_aux_kernels.hpp"
 
 using ns::Cx;
 using ns::EpiArgs;
 using ns::FftPlan;
 using ns::Geom;
+using ns::AdjArgs;
+using ns::LamArgs;
 
 namespace {
 
@@ -64,6 +67,7 @@ struct Layout {
   int ntz;           // k_z tiles over [0, kzn)
   int ntzf;          // k_z tiles over [0, N/2]
   int pz, tz;        // lines per block and threads of the z pass
+  int pa, ta;        // the same for the adjoint z pass (0: adjoint not available)
   long long k2top;   // largest retained |k|^2
   int nsh, nbins;
   std::vector<int2> tiles;
@@ -156,6 +160,12 @@ bool make_layout(const ns_config* c, Layout* lay) {
   while (3 * pz * n > kEptZ * tz) tz *= 2;
   lay->pz = pz;
   lay->tz = tz;
+  int pa = pz;
+  while (pa > 2 && 9 * pa * n > 2 * kEptZ * 512) pa /= 2;
+  int ta = 256;
+  while (9 * pa * n > 2 * kEptZ * ta) ta *= 2;
+  lay->pa = (ta <= 512) ? pa : 0;
+  lay->ta = ta;
   // plan
   FftPlan& p = lay->plan;
   std::memset(&p, 0, sizeof(p));
@@ -188,7 +198,7 @@ bool make_layout(const ns_config* c, Layout* lay) {
   lay->off_etab = take(2 * (size_t)(lay->k2top + 1) * rsz);
   lay->off_force = take(3 * 196 * e);
   lay->off_tiles = take(lay->tiles.size() * sizeof(int2) + 8);
-  lay->off_w = take(6 * (size_t)g.wcomp * e);
+  lay->off_w = take(9 * (size_t)g.wcomp * e);
   lay->off_s = take(3 * (size_t)g.comp * e);
   lay->off_a = take(3 * (size_t)g.comp * e);
   lay->off_spec = take((size_t)kSpecBlocks * lay->nbins * sizeof(double));
@@ -289,6 +299,7 @@ Ptrs<R> ptrs(ns_ctx* c) {
 
 size_t lds_strided(const Layout& l) { return (size_t)(l.g.n + l.g.n * l.g.L) * l.elem; }
 size_t lds_z(const Layout& l) { return (size_t)(l.g.n + 3 * l.pz * l.g.n) * l.elem; }
+size_t lds_zadj(const Layout& l) { return (size_t)(l.g.n + (9 * l.pa * l.g.n) / 2) * l.elem; }
 
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes) {
@@ -491,6 +502,125 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
   return NS_OK;
 }
 
+// One transposed linearised evaluation at state `st` with shift s: lam-pass input
+// from `la`, adjoint stage combination AOP in the last pass.
+template <typename R, int AOP>
+ns_status adj_eval(ns_ctx* c, const Cx<R>* st, const double* s, const LamArgs<R>& la, AdjArgs<R> aa) {
+  const Layout& l = c->lay;
+  const Geom& g = l.g;
+  Ptrs<R> p = ptrs<R>(c);
+  const int shifted = (s != nullptr && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0)) ? 1 : 0;
+  hipError_t e;
+  if (shifted) {
+    const int nt = 2 * g.n + g.h;
+    hipLaunchKernelGGL(ns::k_phase<R>, dim3((nt + 255) / 256), dim3(256), 0, c->stream, p.ph, g.n,
+                       g.h, s[0], s[1], s[2]);
+  }
+  const size_t lds = lds_strided(l);
+  const int ntiles = (int)l.tiles.size();
+  if (ntiles > 0) {
+    auto k1 = ns::k_xinv<R, kEpt>;
+    if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
+    hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, st, p.W, p.tw, p.ph, shifted,
+                       p.tiles, g, l.plan);
+    auto kl = ns::k_xlam<R, kEpt>;
+    if ((e = allow_lds(kl, lds)) != hipSuccess) return hip_check(c, e, "k_xlam attribute");
+    hipLaunchKernelGGL(kl, dim3(ntiles), dim3(l.tx), lds, c->stream, la, p.W, p.tw, p.ph, shifted,
+                       p.tiles, g, l.plan);
+    auto k2 = ns::k_ypass<R, kEpt, +1>;
+    if ((e = allow_lds(k2, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
+    hipLaunchKernelGGL(k2, dim3(9 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
+                       l.plan);
+    const size_t ldsz = lds_zadj(l);
+    auto k3 = ns::k_zadj<R, kEptZ>;
+    if ((e = allow_lds(k3, ldsz)) != hipSuccess) return hip_check(c, e, "k_zadj attribute");
+    hipLaunchKernelGGL(k3, dim3((int)((long long)g.n * g.n / l.pa)), dim3(l.ta), ldsz, c->stream,
+                       p.W, p.tw, l.pa, g, l.plan);
+    auto k4 = ns::k_ypass<R, kEpt, -1>;
+    if ((e = allow_lds(k4, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
+    hipLaunchKernelGGL(k4, dim3(6 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
+                       l.plan);
+  }
+  auto k5 = ns::k_xadj<R, kEpt, AOP>;
+  if ((e = allow_lds(k5, lds)) != hipSuccess) return hip_check(c, e, "k_xadj attribute");
+  const int nblk = aa.full ? g.n * l.ntzf : ntiles;
+  aa.ntzf = l.ntzf;
+  if (nblk > 0)
+    hipLaunchKernelGGL(k5, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, p.ph, shifted, p.tiles, g,
+                       l.plan, aa);
+  return hip_check(c, hipGetLastError(), "adjoint launch");
+}
+
+template <typename R>
+ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, const double* alpha) {
+  const Cx<R>* u0 = static_cast<const Cx<R>*>(u0v);
+  Cx<R>* lam = static_cast<Cx<R>*>(lamv);
+  Ptrs<R> p = ptrs<R>(c);
+  ns_status st = etab<R>(c, dt);
+  if (st != NS_OK) return st;
+  const R rdt = R(dt);
+  auto adj = [&](int full) {
+    AdjArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.eh = p.eh;
+    a.edt = p.edt;
+    a.full = full;
+    return a;
+  };
+  auto lamargs = [&](const Cx<R>* A, R cA, const R* eA, const Cx<R>* B, R cB, const R* eB) {
+    LamArgs<R> la;
+    la.A = A; la.B = B; la.eA = eA; la.eB = eB; la.cA = cA; la.cB = cB;
+    return la;
+  };
+  const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
+  if (variant == NS_PS_EXACT) {
+    EpiArgs<R> f = epi<R>(c, 0);
+    f.dt = rdt;
+    f.out0 = p.ab;
+    if ((st = eval<R, ns::OP_STORE>(c, u0, zero, f)) != NS_OK) return st;
+    f.in0 = u0;
+    f.in1 = p.ab;
+    f.out0 = p.sb;
+    if ((st = eval<R, ns::OP_EX1B>(c, u0, half, f)) != NS_OK) return st;  // sb = S_h
+    LamArgs<R> l1 = lamargs(lam, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
+    AdjArgs<R> a = adj(0);
+    a.out0 = p.ab;
+    if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, zero, l1, a)) != NS_OK) return st;
+    a.in1 = p.ab;
+    if ((st = adj_eval<R, ns::AOP_ACC>(c, p.sb, half, l1, a)) != NS_OK) return st;  // ab = mu
+    LamArgs<R> l2 = lamargs(p.ab, R(0.25) * rdt, p.eh, nullptr, R(0), nullptr);
+    a.in0 = lam;
+    a.in1 = p.ab;
+    a.out0 = lam;
+    if ((st = adj_eval<R, ns::AOP_EXACT>(c, u0, zero, l2, a)) != NS_OK) return st;
+    AdjArgs<R> b = adj(1);
+    b.in1 = lam;
+    b.out0 = lam;
+    return adj_eval<R, ns::AOP_ACC>(c, u0, half, l2, b);
+  }
+  double al[3] = {0, 0, 0};
+  if (variant == NS_PS_RANDOM)
+    for (int j = 0; j < 3; ++j) al[j] = alpha[j];
+  double be[3];
+  for (int j = 0; j < 3; ++j) be[j] = std::fmod(al[j] + 0.5, 1.0);
+  EpiArgs<R> f = epi<R>(c, 0);
+  f.dt = rdt;
+  f.in0 = u0;
+  f.out0 = p.ab;
+  f.out1 = p.sb;
+  if ((st = eval<R, ns::OP_HEUN1>(c, u0, al, f)) != NS_OK) return st;  // sb = S1
+  LamArgs<R> l1 = lamargs(lam, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
+  AdjArgs<R> a = adj(0);
+  a.out0 = p.ab;
+  if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, be, l1, a)) != NS_OK) return st;  // ab = mu1
+  LamArgs<R> l2 = lamargs(lam, R(0.5) * rdt, p.eh, p.ab, rdt, p.edt);
+  AdjArgs<R> b = adj(1);
+  b.in0 = lam;
+  b.in1 = p.ab;
+  b.out0 = lam;
+  return adj_eval<R, ns::AOP_HEUN>(c, u0, al, l2, b);
+}
+
 template <typename R>
 ns_status spectra_t(ns_ctx* c, const void* u, const void* nh, ns_spectra_out* out) {
   const Layout& l = c->lay;
@@ -688,9 +818,18 @@ ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches) {
 
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt, int32_t variant,
                                 const double alpha[3]) {
-  (void)u_hat0; (void)lam; (void)dt; (void)variant; (void)alpha;
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
-  return fail(ctx, NS_ERR_STATE, "ns_vjp_rk2_phaseshift: not built in this library version");
+  if (!aligned(u_hat0) || !aligned(lam)) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must be non-NULL 256-byte aligned device pointers");
+  if (u_hat0 == lam) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must not overlap");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
+  if (variant != NS_PS_EXACT && variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
+    return fail(ctx, NS_ERR_ARG, "unknown phase-shift variant");
+  if (variant == NS_PS_RANDOM && (alpha == nullptr || !std::isfinite(alpha[0]) || !std::isfinite(alpha[1]) ||
+                                  !std::isfinite(alpha[2])))
+    return fail(ctx, NS_ERR_ARG, "NS_PS_RANDOM needs the finite first-stage shift alpha");
+  if (ctx->lay.pa == 0) return fail(ctx, NS_ERR_ARG, "the adjoint supports n <= 910");
+  return ctx->cfg.precision == NS_FP32 ? vjp_t<float>(ctx, u_hat0, lam, dt, variant, alpha)
+                                       : vjp_t<double>(ctx, u_hat0, lam, dt, variant, alpha);
 }
 
 }  // extern "C"
