@@ -81,12 +81,17 @@ typedef struct {
   int32_t n;          /* grid points per direction: 2^a 3^b 5^c, a >= 1, 8 <= n <= 1024 */
   int32_t precision;  /* ns_precision of every field */
   int32_t mask;       /* ns_mask */
-  int32_t reserved;   /* must be 0 */
+  int32_t flags;      /* 0, or NS_CFG_GENERIC_PASSES */
   double nu;          /* kinematic viscosity, >= 0 */
   double ct;          /* truncation coefficient, 0 < ct <= 1 */
   uint64_t seed;      /* seed of the per-step random shifts (NS_PS_RANDOM, alphas == NULL) */
   void* stream;       /* hipStream_t on which all work is enqueued */
 } ns_config;
+
+/* Config flag: always use the size-generic passes (runtime radix plan) instead of
+ * the compile-time specialised FP32 passes for N = 64, 128, 192, 256.  Results
+ * agree to FP32 round-off; meant for testing and comparison. */
+#define NS_CFG_GENERIC_PASSES 1
 
 /* Forcing of the "split" phase-shift scheme (Eq. forcing-eq): a divergence-free
  * random field on the shell k2_lo <= |k|^2 <= k2_hi (only 4..9 supported, the

@@ -1,0 +1,344 @@
+// ns_fast.hpp -- compile-time specialised passes for the common grid sizes (FP32, gfx950).
+//
+// Same scratch layout, tile list and pass semantics as the generic kernels of
+// ns_kernels.hpp; the transforms run on registers (fft_reg.hpp) with one LDS
+// exchange per radix boundary instead of one LDS round trip per stage, and all
+// indices are compile-time except the thread and block coordinates.
+//
+// Strided passes (x, y): a block is one tile of L = 16 contiguous k_z columns;
+// thread (l, t) = (tid mod L, tid div L) handles column l, points of the line
+// owned by t.  LDS: the exchange buffer [position][column] (row pitch L + 1 to
+// spread banks) and the twiddle table.
+// Contiguous pass (z): a block holds P lines, thread (p, t) = (tid div TPL, tid mod TPL).
+#pragma once
+
+#include "fft_reg.hpp"
+#include "ns_kernels.hpp"
+
+namespace ns {
+
+constexpr int kFastL = 16;
+constexpr int kFastLp = kFastL + 1;
+
+// One line plan: N points over TPL threads, inverse and forward radix lists.
+template <int N_, int TPL_, typename Inv_, typename Fwd_>
+struct LinePlan {
+  static constexpr int N = N_;
+  static constexpr int TPL = TPL_;
+  static constexpr int EPT = N_ / TPL_;
+  using Inv = Inv_;   // radices of the inverse transforms
+  using Fwd = Fwd_;   // radices of the forward transforms (reverse order of Inv)
+};
+
+// Plans of the five passes of one size; PZ = lines per block of the z pass.
+template <typename XI, typename YP, typename ZP, int PZ_, typename XF>
+struct FastCfg {
+  static constexpr int N = XI::N;
+  static constexpr int PZ = PZ_;
+  using XInv = XI;
+  using Y = YP;
+  using Z = ZP;
+  using XFwd = XF;
+};
+
+// ------------------------------------------------------------------ x inverse
+// One (tile, field) per block.  Blocks are dispatched round-robin over the 8
+// XCDs; block b works on tile 8 (b div 48) + (b mod 8) and field (b div 8) mod 6,
+// so the six blocks of a tile run back to back on one XCD and re-read the state
+// from its L2.  The tile list is padded to a multiple of 8 with empty tiles.
+template <typename C>
+__global__ void __launch_bounds__(kFastL * C::TPL)
+f_xinv(const Cx<float>* __restrict__ S, Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg,
+       const Cx<float>* __restrict__ ph, int shifted, const int2* __restrict__ tiles, Geom g) {
+  constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
+  using F = RegFft<N, TPL, +1, typename C::Inv>;
+  __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> xb[N * kFastLp];
+  const int tid = threadIdx.x;
+  const int l = tid % kFastL, t = tid / kFastL;
+  const int b = blockIdx.x;
+  const int f = (b >> 3) % 6;
+  const int2 tile = tiles[8 * (b / 48) + (b & 7)];
+  const int yi = tile.x, kz = tile.y + l;
+  const int ky = kval(yi, N);
+  for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
+  const bool col = kz < g.kzn;
+  Cx<float> phyz = cx(1.f, 0.f);
+  if (shifted && col) phyz = cmul(ph[N + yi], ph[2 * N + kz]);
+  const LineView<float, kFastLp> lv{xb + l};
+  const long long sbase = (long long)yi * g.h + kz;
+  // field f = sum_c coef_c(k) u_c: u_x, u_y, u_z, then omega = i k x u
+  const int c1 = (f < 3) ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
+  const int c2 = (f == 3) ? 1 : (f == 4 ? 2 : 0);
+  const float kyf = float(ky), kzf = float(kz);
+  Cx<float> v[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int p = F::in_pos(t, i);
+    const int kx = kval(p, N);
+    Cx<float> val = cx(0.f, 0.f);
+    if (col && retained(g, kx, ky, kz)) {
+      const long long idx = (long long)p * N * g.h + sbase;
+      const Cx<float> a1 = S[c1 * g.comp + idx];
+      if (f < 3) {
+        val = a1;
+      } else {
+        const Cx<float> a2 = S[c2 * g.comp + idx];
+        const float kxf = float(kx);
+        // omega_x = i(ky u_z - kz u_y), omega_y = i(kz u_x - kx u_z), omega_z = i(kx u_y - ky u_x)
+        const float w1 = (f == 3) ? kyf : (f == 4 ? kzf : kxf);
+        const float w2 = (f == 3) ? kzf : (f == 4 ? kxf : kyf);
+        val = mul_i(scale(a1, w1) - scale(a2, w2));
+      }
+      if (shifted) val = cmul(val, cmul(ph[p], phyz));
+    }
+    v[i] = val;
+  }
+  F::run(v, t, lv, tw);
+  if (col) {
+    Cx<float>* out = W + f * g.wcomp + (long long)yi * g.kzp + kz;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) out[(long long)F::out_pos(t, i) * N * g.kzp] = v[i];
+  }
+}
+
+// ------------------------------------------------------------------ y passes (in place)
+template <typename C, int S>
+__global__ void __launch_bounds__(kFastL * C::TPL)
+f_ypass(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, Geom g) {
+  constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
+  using F = RegFft<N, TPL, S, std::conditional_t<(S > 0), typename C::Inv, typename C::Fwd>>;
+  __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> xb[N * kFastLp];
+  const int tid = threadIdx.x;
+  const int l = tid % kFastL, t = tid / kFastL;
+  const int b = blockIdx.x;
+  const int kzt = b % ntz, rest = b / ntz;
+  const int x = rest % N, f = rest / N;
+  const int kz0 = kzt * kFastL, kz = kz0 + l;
+  const int yb = ybound(g, kz0);
+  for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
+  const bool col = kz < g.kzn;
+  Cx<float>* base = W + f * g.wcomp + (long long)x * N * g.kzp + kz;
+  const LineView<float, kFastLp> lv{xb + l};
+  Cx<float> v[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int p = F::in_pos(t, i);
+    v[i] = (col && (S < 0 || abs(kval(p, N)) <= yb)) ? base[(long long)p * g.kzp] : cx(0.f, 0.f);
+  }
+  F::run(v, t, lv, tw);
+  if (col) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = F::out_pos(t, i);
+      if (S > 0 || abs(kval(p, N)) <= yb) base[(long long)p * g.kzp] = v[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ z fused
+// P lines per block.  Inverse slices (u_x + i u_y), (u_z + i w_x), (w_y + i w_z) built
+// from the half spectra on the fly (Z(k) = a(k) + i b(k), Z(N-k) = conj a(k) + i conj b(k),
+// imaginary parts of the k_z = 0 and N/2 coefficients dropped); the product
+// f = u x omega stays in registers; forward slices (f_x + i f_y) and f_z; the
+// spectra are split through LDS.  Output scratch fields 0, 1, 2 = f_x, f_y, f_z (unnormalised).
+template <typename C, int P>
+__global__ void __launch_bounds__(P * C::TPL)
+f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
+  constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT, HN = N / 2, NT = P * TPL;
+  using FI = RegFft<N, TPL, +1, typename C::Inv>;
+  using FF = RegFft<N, TPL, -1, typename C::Fwd>;
+  static_assert(FI::RL == FF::R0, "the forward transform must start with the last inverse radix");
+  __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> xb[P * (N + 1)];  // exchanges, then the spectrum of f_z
+  __shared__ Cx<float> sp[P * N];        // spectrum of f_x + i f_y
+  const int tid = threadIdx.x;
+  const int p = tid / TPL, t = tid % TPL;
+  const long long line = (long long)blockIdx.x * P + p;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const LineView<float, 1> lv{xb + p * (N + 1)};
+  const Cx<float>* src = W + line * g.kzp;
+  float fx[EPT], fy[EPT], fz[EPT];
+  Cx<float> z[2][EPT];
+  Cx<float> v[EPT];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int pos = FI::in_pos(t, i);
+      const int k = pos <= HN ? pos : N - pos;
+      Cx<float> a = cx(0.f, 0.f), bb = cx(0.f, 0.f);
+      if (k < g.kzn) {
+        a = src[(2 * q) * g.wcomp + k];
+        bb = src[(2 * q + 1) * g.wcomp + k];
+      }
+      if (pos == 0 || pos == HN) v[i] = cx(a.re, bb.re);
+      else if (pos < HN) v[i] = cx(a.re - bb.im, a.im + bb.re);
+      else v[i] = cx(a.re + bb.im, bb.re - a.im);
+    }
+    FI::run(v, t, lv, tw);
+    if (q < 2) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) z[q][i] = v[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const float ux = z[0][i].re, uy = z[0][i].im, uz = z[1][i].re, wx = z[1][i].im;
+    const float wy = v[i].re, wz = v[i].im;
+    fx[i] = uy * wz - uz * wy;
+    fy[i] = uz * wx - ux * wz;
+    fz[i] = ux * wy - uy * wx;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) v[i] = cx(fx[i], fy[i]);
+  FF::run(v, t, lv, tw);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) sp[p * N + FF::out_pos(t, i)] = v[i];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) v[i] = cx(fz[i], 0.f);
+  FF::run(v, t, lv, tw);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) xb[p * (N + 1) + FF::out_pos(t, i)] = v[i];
+  __syncthreads();
+  const long long line0 = (long long)blockIdx.x * P;
+  for (int idx = tid; idx < P * g.kzn; idx += NT) {
+    const int k = idx % g.kzn, pp = idx / g.kzn;
+    const Cx<float> c1 = sp[pp * N + k], c2 = sp[pp * N + ((N - k) % N)];
+    const long long off = (line0 + pp) * g.kzp + k;
+    W[off] = cx(0.5f * (c1.re + c2.re), 0.5f * (c1.im - c2.im));
+    W[g.wcomp + off] = cx(0.5f * (c1.im + c2.im), -0.5f * (c1.re - c2.re));
+    W[2 * g.wcomp + off] = xb[pp * (N + 1) + k];
+  }
+}
+
+// ------------------------------------------------------------------ x forward + epilogue
+template <typename C, int OP>
+__global__ void __launch_bounds__(kFastL * C::TPL)
+f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, const Cx<float>* __restrict__ ph,
+       int shifted, const int2* __restrict__ tiles, Geom g, EpiArgs<float> a) {
+  constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
+  using F = RegFft<N, TPL, -1, typename C::Fwd>;
+  __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> xb[N * kFastLp];
+  const int tid = threadIdx.x;
+  const int l = tid % kFastL, t = tid / kFastL;
+  int yi, kz0;
+  if (a.full) {
+    yi = blockIdx.x / a.ntzf;
+    kz0 = (blockIdx.x % a.ntzf) * kFastL;
+  } else {
+    const int2 tile = tiles[blockIdx.x];
+    yi = tile.x;
+    kz0 = tile.y;
+  }
+  const int kz = kz0 + l;
+  const int ky = kval(yi, N);
+  const bool active = line_active(g, ky, kz0);
+  const LineView<float, kFastLp> lv{xb + l};
+  Cx<float> r[3][EPT];
+  if (active) {
+    for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
+    const bool col = kz < g.kzn;
+    const Cx<float>* src = W + (long long)yi * g.kzp + kz;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        r[f][i] = col ? src[f * g.wcomp + (long long)F::in_pos(t, i) * N * g.kzp] : cx(0.f, 0.f);
+      F::run(r[f], t, lv, tw);
+    }
+  }
+  if (kz >= g.h || (!a.full && kz >= g.kzn)) return;
+  const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
+  Cx<float> phyz = cx(1.f, 0.f);
+  if (shifted && active && kz < g.kzn) phyz = cmul(ph[N + yi], ph[2 * N + kz]);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int p = F::out_pos(t, i);
+    const int kx = kval(p, N);
+    const long long idx = ((long long)p * N + yi) * g.h + kz;
+    const bool ret = active && kz < g.kzn && retained(g, kx, ky, kz);
+    if (!ret) {
+      for (int c = 0; c < 3; ++c) {
+        a.out0[c * g.comp + idx] = cx(0.f, 0.f);
+        if (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2)
+          a.out1[c * g.comp + idx] = cx(0.f, 0.f);
+      }
+      continue;
+    }
+    Cx<float> Fv[3] = {scale(r[0][i], inv_n3), scale(r[1][i], inv_n3), scale(r[2][i], inv_n3)};
+    if (shifted) {
+      const Cx<float> phi = cmul(ph[p], phyz);
+      Fv[0] = cmulc(Fv[0], phi);
+      Fv[1] = cmulc(Fv[1], phi);
+      Fv[2] = cmulc(Fv[2], phi);
+    }
+    const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
+    if (k2 == 0) {
+      Fv[0] = Fv[1] = Fv[2] = cx(0.f, 0.f);
+    } else {
+      const float rk2 = 1.f / float(k2);
+      const float kxr = float(kx), kyr = float(ky), kzr = float(kz);
+      const Cx<float> kd = scale(scale(Fv[0], kxr) + scale(Fv[1], kyr) + scale(Fv[2], kzr), rk2);
+      Fv[0] = Fv[0] - scale(kd, kxr);
+      Fv[1] = Fv[1] - scale(kd, kyr);
+      Fv[2] = Fv[2] - scale(kd, kzr);
+    }
+    float eh = 1.f, edt = 1.f;
+    if (OP >= OP_HEUN1) { eh = a.eh[k2]; edt = a.edt[k2]; }
+    const float dt = a.dt;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long o = c * g.comp + idx;
+      const Cx<float> Nv = Fv[c];
+      if (OP == OP_STORE) {
+        a.out0[o] = Nv;
+      } else if (OP == OP_AVG) {
+        a.out0[o] = scale(a.in1[o] + Nv, 0.5f);
+      } else if (OP == OP_HEUN1) {
+        Cx<float> O = cx(0.f, 0.f);
+        if (a.force != nullptr && k2 >= 4 && k2 <= 9) O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
+        const Cx<float> s0 = a.in0[o];
+        a.out1[o] = scale(s0 + scale(Nv + O, dt), edt);
+        a.out0[o] = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
+      } else if (OP == OP_HEUN2) {
+        a.out0[o] = a.in1[o] + scale(Nv, 0.5f * dt * eh);
+      } else if (OP == OP_EX1B) {
+        a.out0[o] = scale(a.in0[o] + scale(a.in1[o] + Nv, 0.25f * dt), eh);
+      } else if (OP == OP_EX2B) {
+        a.out0[o] = scale(a.in0[o], edt) + scale(a.in1[o] + Nv, 0.5f * dt * eh);
+      } else if (OP == OP_RK4_0) {
+        const Cx<float> s0 = a.in0[o];
+        a.out1[o] = scale(s0 + scale(Nv, 0.5f * dt), eh);
+        a.out0[o] = scale(s0 + scale(Nv, dt / 6.f), edt);
+      } else if (OP == OP_RK4_1) {
+        const Cx<float> s0 = a.in0[o];
+        a.out1[o] = scale(s0, eh) + scale(Nv, 0.5f * dt);
+        a.out0[o] = a.in1[o] + scale(Nv, dt / 3.f * eh);
+      } else if (OP == OP_RK4_2) {
+        const Cx<float> s0 = a.in0[o];
+        a.out1[o] = scale(s0, edt) + scale(Nv, dt * eh);
+        a.out0[o] = a.in1[o] + scale(Nv, dt / 3.f * eh);
+      } else {
+        a.out0[o] = a.in1[o] + scale(Nv, dt / 6.f);
+      }
+    }
+  }
+}
+
+// Specialised sizes (FP32).  The forward radix list is the inverse one reversed.
+using LP64 = LinePlan<64, 8, Radices<8, 8>, Radices<8, 8>>;
+using LP128a = LinePlan<128, 8, Radices<8, 16>, Radices<16, 8>>;
+using LP128b = LinePlan<128, 16, Radices<8, 4, 4>, Radices<4, 4, 8>>;
+using LP192 = LinePlan<192, 16, Radices<12, 4, 4>, Radices<4, 4, 12>>;
+using LP256a = LinePlan<256, 16, Radices<16, 16>, Radices<16, 16>>;
+using LP256b = LinePlan<256, 32, Radices<8, 8, 4>, Radices<4, 8, 8>>;
+using Fast64 = FastCfg<LP64, LP64, LP64, 16, LP64>;
+using Fast128 = FastCfg<LP128a, LP128a, LP128b, 16, LP128b>;
+using Fast192 = FastCfg<LP192, LP192, LP192, 8, LP192>;
+using Fast256 = FastCfg<LP256a, LP256a, LP256b, 8, LP256b>;
+
+}  // namespace ns

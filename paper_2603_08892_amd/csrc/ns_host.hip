@@ -8,13 +8,16 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/ns.h"
 #include "ns_adjoint.hpp"
+#include "ns_fast.hpp"
 #include "ns_aux_kernels.hpp"
 
 using ns::Cx;
@@ -70,7 +73,8 @@ struct Layout {
   int pa, ta;        // the same for the adjoint z pass (0: adjoint not available)
   long long k2top;   // largest retained |k|^2
   int nsh, nbins;
-  std::vector<int2> tiles;
+  std::vector<int2> tiles;   // active (k_y index, k_z tile start), padded to a multiple of 8
+  int ntiles_active;
   size_t off_tw, off_ph, off_etab, off_force, off_tiles, off_w, off_s, off_a, off_spec, off_specout;
   size_t total;
 };
@@ -107,7 +111,7 @@ const char* validate(const ns_config* c) {
   if (!factor_ok(c->n, nullptr)) return "n must be 2^a 3^b 5^c with a >= 1 and 8 <= n <= 1024";
   if (c->precision != NS_FP32 && c->precision != NS_FP64) return "precision must be NS_FP32 or NS_FP64";
   if (c->mask != NS_MASK_SPHERE && c->mask != NS_MASK_CUBE) return "mask must be NS_MASK_SPHERE or NS_MASK_CUBE";
-  if (c->reserved != 0) return "reserved must be 0";
+  if (c->flags & ~NS_CFG_GENERIC_PASSES) return "unknown config flags";
   if (!(c->nu >= 0.0) || !std::isfinite(c->nu)) return "nu must be finite and >= 0";
   if (!(c->ct > 0.0 && c->ct <= 1.0)) return "ct must satisfy 0 < ct <= 1";
   const double kmax = c->ct * c->n / 2.0;
@@ -187,6 +191,8 @@ bool make_layout(const ns_config* c, Layout* lay) {
       if (kz0 < g.kzn && std::abs(ky) <= ybound_host(g, kz0)) lay->tiles.push_back(make_int2(yi, kz0));
     }
   }
+  lay->ntiles_active = (int)lay->tiles.size();
+  while (lay->tiles.size() % 8 != 0) lay->tiles.push_back(make_int2(0, 1 << 20));
   lay->nsh = num_shells(n);
   lay->nbins = 3 * lay->nsh + 3 * g.h + 5;
   // workspace
@@ -216,6 +222,7 @@ struct ns_ctx {
   char* ws;
   std::string err;
   std::vector<double> host_spec;
+  int fast = 0;       // N of the specialised FP32 passes in use (0: generic passes)
   // per-pass timing: events[2 i], events[2 i + 1] bracket launch i of pass tpass[i]
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -315,11 +322,48 @@ hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, int shifted, const EpiArgs<R
   auto kern = ns::k_xfwd<R, kEpt, OP>;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
-  const int nblk = a.full ? l.g.n * l.ntzf : (int)l.tiles.size();
+  const int nblk = a.full ? l.g.n * l.ntzf : l.ntiles_active;
   if (nblk == 0) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, p.ph, shifted,
                      p.tiles, l.g, l.plan, a);
   return hipGetLastError();
+}
+
+// Specialised FP32 passes for one compile-time size (same semantics and layout).
+template <typename C, int OP>
+ns_status eval_fast(ns_ctx* c, const Cx<float>* in, int shifted, const EpiArgs<float>& a) {
+  const Layout& l = c->lay;
+  const Geom& g = l.g;
+  Ptrs<float> p = ptrs<float>(c);
+  constexpr int N = C::N, P = C::PZ;
+  hipError_t e;
+  const int ntiles = l.ntiles_active;
+  if (ntiles > 0) {
+    const int padded = (ntiles + 7) / 8 * 8;
+    if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
+    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(6 * padded), dim3(ns::kFastL * C::XInv::TPL), 0,
+                       c->stream, in, p.W, p.tw, p.ph, shifted, p.tiles, g);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+    if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
+    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
+                       c->stream, p.W, p.tw, l.ntz, g);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+    if ((e = tstart(c, 2)) != hipSuccess) return hip_check(c, e, "timing event");
+    hipLaunchKernelGGL((ns::f_zcross<typename C::Z, P>), dim3(N * N / P), dim3(P * C::Z::TPL), 0, c->stream,
+                       p.W, p.tw, g);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+    if ((e = tstart(c, 3)) != hipSuccess) return hip_check(c, e, "timing event");
+    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, -1>), dim3(3 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
+                       c->stream, p.W, p.tw, l.ntz, g);
+    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+  }
+  const int nblk = a.full ? N * l.ntzf : ntiles;
+  if ((e = tstart(c, 4)) != hipSuccess) return hip_check(c, e, "timing event");
+  if (nblk > 0)
+    hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
+                       c->stream, p.W, p.tw, p.ph, shifted, p.tiles, g, a);
+  if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+  return hip_check(c, hipGetLastError(), "nonlinear-term launch");
 }
 
 // One evaluation of the nonlinear term on the state-layout array `in` with the
@@ -336,8 +380,17 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, const double* s, EpiArgs<R> a) {
     hipLaunchKernelGGL(ns::k_phase<R>, dim3((nt + 255) / 256), dim3(256), 0, c->stream, p.ph, g.n,
                        g.h, s[0], s[1], s[2]);
   }
+  if constexpr (std::is_same<R, float>::value) {
+    switch (c->fast) {
+      case 64: return eval_fast<ns::Fast64, OP>(c, in, shifted, a);
+      case 128: return eval_fast<ns::Fast128, OP>(c, in, shifted, a);
+      case 192: return eval_fast<ns::Fast192, OP>(c, in, shifted, a);
+      case 256: return eval_fast<ns::Fast256, OP>(c, in, shifted, a);
+      default: break;
+    }
+  }
   const size_t lds = lds_strided(l);
-  const int ntiles = (int)l.tiles.size();
+  const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
     auto k1 = ns::k_xinv<R, kEpt>;
     if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
@@ -517,7 +570,7 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, const double* s, const LamArgs<R>
                        g.h, s[0], s[1], s[2]);
   }
   const size_t lds = lds_strided(l);
-  const int ntiles = (int)l.tiles.size();
+  const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
     auto k1 = ns::k_xinv<R, kEpt>;
     if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
@@ -692,6 +745,9 @@ ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx
     return fail(nullptr, NS_ERR_SIZE, msg);
   }
   c->ws = static_cast<char*>(workspace);
+  if (cfg->precision == NS_FP32 && c->lay.g.L == ns::kFastL &&
+      (cfg->n == 64 || cfg->n == 128 || cfg->n == 192 || cfg->n == 256) && !(cfg->flags & NS_CFG_GENERIC_PASSES))
+    c->fast = cfg->n;
   // twiddles W_N^t = exp(-2 pi i t/N), long double, rounded once
   const int n = cfg->n;
   const long double pi = 3.141592653589793238462643383279502884L;

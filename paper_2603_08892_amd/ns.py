@@ -34,7 +34,7 @@ PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilo
 
 class NSConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("precision", ctypes.c_int32), ("mask", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("nu", ctypes.c_double), ("ct", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("nu", ctypes.c_double), ("ct", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
 
 
@@ -90,10 +90,13 @@ def lib():
     return L
 
 
-def make_config(n, nu, ct, mask="sphere", precision="fp32", seed=0, stream=None):
+NS_CFG_GENERIC_PASSES = 1
+
+
+def make_config(n, nu, ct, mask="sphere", precision="fp32", seed=0, stream=None, generic=False):
     return NSConfig(int(n), NS_FP32 if precision == "fp32" else NS_FP64,
-                    NS_MASK_SPHERE if mask == "sphere" else NS_MASK_CUBE, 0, float(nu), float(ct),
-                    int(seed), stream)
+                    NS_MASK_SPHERE if mask == "sphere" else NS_MASK_CUBE,
+                    NS_CFG_GENERIC_PASSES if generic else 0, float(nu), float(ct), int(seed), stream)
 
 
 def workspace_bytes(n, nu, ct, mask="sphere", precision="fp32"):
@@ -118,14 +121,14 @@ def _dbl3(v):
 class Solver:
     """One library context on a CUDA (HIP) device with its workspace tensor."""
 
-    def __init__(self, n, nu, ct, mask="sphere", precision="fp32", seed=0, device="cuda:0"):
+    def __init__(self, n, nu, ct, mask="sphere", precision="fp32", seed=0, device="cuda:0", generic=False):
         import torch
         self.torch = torch
         self.n, self.nu, self.ct, self.mask, self.precision = n, nu, ct, mask, precision
         self.device = torch.device(device)
         self.dtype = torch.complex64 if precision == "fp32" else torch.complex128
         self.stream = torch.cuda.current_stream(self.device)
-        cfg = make_config(n, nu, ct, mask, precision, seed, ctypes.c_void_p(self.stream.cuda_stream))
+        cfg = make_config(n, nu, ct, mask, precision, seed, ctypes.c_void_p(self.stream.cuda_stream), generic)
         L = lib()
         nbytes = L.ns_workspace_bytes(ctypes.byref(cfg))
         if nbytes == 0:

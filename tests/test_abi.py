@@ -62,8 +62,10 @@ def test_invalid_nu_and_precision_rejected():
     cfg.precision = 7
     assert L.ns_workspace_bytes(ctypes.byref(cfg)) == 0
     cfg = ns.make_config(32, 0.1, 1.0)
-    cfg.reserved = 1
+    cfg.flags = 6
     assert L.ns_workspace_bytes(ctypes.byref(cfg)) == 0
+    cfg.flags = ns.NS_CFG_GENERIC_PASSES
+    assert L.ns_workspace_bytes(ctypes.byref(cfg)) > 0
 
 
 def test_init_argument_errors_before_any_hip_call():

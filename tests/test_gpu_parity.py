@@ -4,7 +4,7 @@ seeded inputs.
 Tolerances: FP64 instantiation 1e-12 (relative L2 and relative to the largest
 entry).  FP32 fields: 1e-5 relative L2 per evaluation or per step (the stated
 FP32 field tolerance; FP32 round-off of ~log2(N^3) butterfly stages and one
-product gives ~1e-6 here), and 1e-4 relative to the largest entry: the
+product gives 2e-6 to 5e-6 here), and 3e-4 relative to the largest entry: the
 projection removes the gradient part of u x omega, which on some high-|k|
 modes is one to two orders of magnitude larger than the solenoidal remainder,
 so the per-mode FP32 error is amplified there by |FFT(u x omega)| / |N|.
@@ -22,12 +22,12 @@ from paper_2603_08892_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 3e-4)}
 
 
-def _solver(n, ct, mask="sphere", prec="fp32", nu=0.01, seed=0):
+def _solver(n, ct, mask="sphere", prec="fp32", nu=0.01, seed=0, generic=False):
     from paper_2603_08892_amd import ns
-    return ns.Solver(n, nu, ct, mask=mask, precision=prec, seed=seed)
+    return ns.Solver(n, nu, ct, mask=mask, precision=prec, seed=seed, generic=generic)
 
 
 def _rep(a, prec):
@@ -57,6 +57,7 @@ NL_CASES = [
     (24, 1.0, "cube", "fp64"), (32, 2 / 3, "sphere", "fp64"), (40, 0.9, "sphere", "fp64"),
     (48, 1.0, "sphere", "fp32"), (32, 1.0, "sphere", "fp32"), (60, 2 / 3, "cube", "fp32"),
     (64, 1.0, "sphere", "fp32"), (96, 2 / 3, "sphere", "fp32"), (128, 1.0, "sphere", "fp32"),
+    (128, 2 / 3, "cube", "fp32"), (192, 2 / 3, "sphere", "fp32"), (256, 1.0, "sphere", "fp32"),
 ]
 
 
@@ -266,3 +267,28 @@ def test_energy_conservation_on_gpu():
         nh = _host(s.nonlinear(ud, shift=shift))
         scale = np.sqrt(spectra.inner(u, u) * spectra.inner(nh, nh))
         assert abs(spectra.inner(u, nh)) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("n,ct", [(64, 1.0), (128, 1.0), (128, 2 / 3), (192, 2 / 3), (256, 1.0)])
+def test_specialised_passes_match_generic(n, ct):
+    """The compile-time FP32 passes (N = 64, 128, 192, 256) and the size-generic passes
+    agree to FP32 round-off (each is within ~5e-6 of the FP64 oracle), for the
+    nonlinear term and two steps of every scheme."""
+    print(f"[fast-vs-generic] n={n} ct={ct:.4f}", flush=True)
+    nu, dt = 1 / 1600, 2e-3
+    fast = _solver(n, ct, nu=nu, seed=4)
+    gen = _solver(n, ct, nu=nu, seed=4, generic=True)
+    u = _rep(_field(n, ct, "sphere", 77, energy=0.5), "fp32")
+    for shift in [None, (0.5, 0.5, 0.5), (0.3, 0.8, 0.45)]:
+        a = _host(fast.nonlinear(fast.to_device(u), shift=shift))
+        b = _host(gen.nonlinear(gen.to_device(u), shift=shift))
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5, shift
+    for scheme in ("rk4", "exact", "approx", "random"):
+        ua, ub = fast.to_device(u), gen.to_device(u)
+        for s_, ud in ((fast, ua), (gen, ub)):
+            if scheme == "rk4":
+                s_.step_rk4(ud, dt, 2)
+            else:
+                s_.step_ps(ud, dt, 2, scheme)
+        a, b = _host(ua), _host(ub)
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-6, scheme
