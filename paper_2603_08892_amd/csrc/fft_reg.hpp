@@ -116,12 +116,20 @@ __device__ __forceinline__ void rdft(Cx<T>* a) {
 }
 
 // ---------------------------------------------------------------- LDS views of a line
-// Point `pos` of the line at base[pos * ES].
+// Point `pos` of the line at base[pos * ES] (ES > 1: lines interleaved with pitch
+// ES), or, for ES == 1 (contiguous lines), at base[pos + pos / 16]: one padding
+// element every 16 points so that the stride-R writes of the early stages spread
+// over the LDS banks.
 template <typename T, int ES>
 struct LineView {
   Cx<T>* base;
-  __device__ __forceinline__ Cx<T>& at(int pos) const { return base[pos * ES]; }
+  __device__ __forceinline__ Cx<T>& at(int pos) const {
+    if constexpr (ES == 1) return base[pos + (pos >> 4)];
+    else return base[pos * ES];
+  }
 };
+// LDS elements of one contiguous line of n points in the ES == 1 layout
+__host__ __device__ constexpr int line_pitch(int n) { return n + n / 16 + 1; }
 
 // Stages of one transform on the registers v[b * R + m] (b < EPT/R) of thread t.
 // NS = points already combined.  Twiddles from the table tw[] (W_N^t, t < N).

@@ -24,18 +24,19 @@ struct LamArgs {
   const R* eA;
   const R* eB;
   R cA, cB;
+  Lay la, lb;  // layouts of A and B
 };
 
 // ------------------------------------------------------------------ k_xlam
 // Same tiling as k_xinv; writes scratch fields 6, 7, 8.
 template <typename R, int EPT>
 __global__ void __launch_bounds__(512)
-k_xlam(LamArgs<R> la, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg,
-       const Cx<R>* __restrict__ ph, int shifted, const int2* __restrict__ tiles, Geom g,
-       FftPlan plan) {
+k_xlam(LamArgs<R> la, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
+       const int2* __restrict__ tiles, Geom g, FftPlan plan) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem_raw);
-  Cx<R>* buf = tw + g.n;
+  Cx<R>* phx = tw + g.n;
+  Cx<R>* buf = phx + g.n;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = g.n, L = g.L;
   const int2 tile = tiles[blockIdx.x];
@@ -43,6 +44,9 @@ k_xlam(LamArgs<R> la, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg,
   const int ky = kval(yi, n);
   const int npts = n * L;
   for (int t = tid; t < n; t += nt) tw[t] = twg[t];
+  if (sh.on) phase_row(phx, n, sh.s[0], tid, nt);
+  __syncthreads();
+  const Cx<R> phy = sh.on ? phase1<R>(ky, sh.s[1], n) : cx(R(1), R(0));
   Cx<R> v[3][EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -52,14 +56,15 @@ k_xlam(LamArgs<R> la, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg,
       const int p = e >> g.lgL, l = e & (L - 1);
       const int kz = kz0 + l, kx = kval(p, n);
       if (kz < g.kzn && retained(g, kx, ky, kz)) {
-        const long long idx = ((long long)p * n + yi) * g.h + kz;
+        const long long ia = lay_at(la.la, p, yi, kz, n);
         const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
         R fa = la.cA * (la.eA ? la.eA[k2] : R(1));
         Cx<R> q[3];
-        for (int c = 0; c < 3; ++c) q[c] = scale(la.A[c * g.comp + idx], fa);
+        for (int c = 0; c < 3; ++c) q[c] = scale(la.A[c * la.la.cs + ia], fa);
         if (la.B != nullptr) {
+          const long long ib = lay_at(la.lb, p, yi, kz, n);
           const R fb = la.cB * (la.eB ? la.eB[k2] : R(1));
-          for (int c = 0; c < 3; ++c) q[c] = q[c] + scale(la.B[c * g.comp + idx], fb);
+          for (int c = 0; c < 3; ++c) q[c] = q[c] + scale(la.B[c * la.lb.cs + ib], fb);
         }
         if (k2 == 0) {
           q[0] = q[1] = q[2] = cx(R(0), R(0));
@@ -71,8 +76,8 @@ k_xlam(LamArgs<R> la, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg,
           q[1] = q[1] - scale(kd, kyr);
           q[2] = q[2] - scale(kd, kzr);
         }
-        if (shifted) {
-          const Cx<R> phi = cmul(ph[p], cmul(ph[n + yi], ph[2 * n + kz]));
+        if (sh.on) {
+          const Cx<R> phi = cmul(phx[p], cmul(phy, phase1<R>(kz, sh.s[2], n)));
           for (int c = 0; c < 3; ++c) q[c] = cmul(q[c], phi);
         }
         v[0][i] = q[0];
@@ -209,17 +214,19 @@ struct AdjArgs {
   const R* edt;
   int full;
   int ntzf;
+  Lay lo0, li0, li1;  // layouts of out0, in0, in1
 };
 
 // Forward x pass of g1 = FFT(omega x lt) and g2 = FFT(lt x u):
 // V = M conj(phi) (g1 + i k x g2) / N^3, then the adjoint stage combination.
 template <typename R, int EPT, int OP>
 __global__ void __launch_bounds__(512)
-k_xadj(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* __restrict__ ph,
-       int shifted, const int2* __restrict__ tiles, Geom g, FftPlan plan, AdjArgs<R> a) {
+k_xadj(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
+       const int2* __restrict__ tiles, Geom g, FftPlan plan, AdjArgs<R> a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem_raw);
-  Cx<R>* buf = tw + g.n;
+  Cx<R>* phx = tw + g.n;
+  Cx<R>* buf = phx + g.n;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = g.n, L = g.L;
   int yi, kz0;
@@ -237,6 +244,7 @@ k_xadj(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* 
   Cx<R> r[3][EPT];
   if (active) {
     for (int t = tid; t < n; t += nt) tw[t] = twg[t];
+    if (sh.on) phase_row(phx, n, sh.s[0], tid, nt);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       if (f > 0) __syncthreads();
@@ -283,26 +291,28 @@ k_xadj(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* 
     const int kz = kz0 + l;
     if (kz >= g.h || (!a.full && kz >= g.kzn)) continue;
     const int kx = kval(p, n);
-    const long long idx = ((long long)p * n + yi) * g.h + kz;
+    const long long io0 = lay_at(a.lo0, p, yi, kz, n);
     const bool ret = active && kz < g.kzn && retained(g, kx, ky, kz);
     if (!ret) {
-      for (int c = 0; c < 3; ++c) a.out0[c * g.comp + idx] = cx(R(0), R(0));
+      if (a.full)
+        for (int c = 0; c < 3; ++c) a.out0[c * a.lo0.cs + io0] = cx(R(0), R(0));
       continue;
     }
+    const long long ii0 = lay_at(a.li0, p, yi, kz, n), ii1 = lay_at(a.li1, p, yi, kz, n);
     Cx<R> V[3] = {scale(r[0][i], inv_n3), scale(r[1][i], inv_n3), scale(r[2][i], inv_n3)};
-    if (shifted) {
-      const Cx<R> phi = cmul(cmul(ph[p], ph[n + yi]), ph[2 * n + kz]);
+    if (sh.on) {
+      const Cx<R> phi = cmul(cmul(phx[p], phase1<R>(ky, sh.s[1], n)), phase1<R>(kz, sh.s[2], n));
       for (int c = 0; c < 3; ++c) V[c] = cmulc(V[c], phi);
     }
     const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
     const R eh = a.eh[k2], edt = a.edt[k2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const long long o = c * g.comp + idx;
+      const long long o = c * a.lo0.cs + io0, i0 = c * a.li0.cs + ii0, i1 = c * a.li1.cs + ii1;
       if (OP == AOP_STORE) a.out0[o] = V[c];
-      else if (OP == AOP_ACC) a.out0[o] = a.in1[o] + V[c];
-      else if (OP == AOP_HEUN) a.out0[o] = scale(a.in0[o] + a.in1[o], edt) + V[c];
-      else a.out0[o] = scale(a.in0[o], edt) + scale(a.in1[o], eh) + V[c];
+      else if (OP == AOP_ACC) a.out0[o] = a.in1[i1] + V[c];
+      else if (OP == AOP_HEUN) a.out0[o] = scale(a.in0[i0] + a.in1[i1], edt) + V[c];
+      else a.out0[o] = scale(a.in0[i0], edt) + scale(a.in1[i1], eh) + V[c];
     }
   }
 }

@@ -89,14 +89,18 @@ k_spectra(const Cx<R>* __restrict__ u, const Cx<R>* __restrict__ nh, double nu, 
   for (int t = threadIdx.x; t < nb; t += blockDim.x) out[t] = bins[t];
 }
 
-// Pass 2: fixed-order sum over the blocks' partials, one thread per bin.
-__global__ void k_spectra_sum(const double* __restrict__ partials, int nblocks, int nb,
-                              double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nb) return;
+// Pass 2: fixed-order sum over the blocks' partials.  Eight bins per block of 256
+// threads; the 32 lanes of a bin sum the partials b = lane, lane + 32, ... in
+// order, then a fixed shuffle tree combines the lanes (deterministic).
+__global__ void __launch_bounds__(256)
+k_spectra_sum(const double* __restrict__ partials, int nblocks, int nb, double* __restrict__ out) {
+  const int bin = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int lane = threadIdx.x & 31;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partials[(long long)b * nb + t];
-  out[t] = s;
+  if (bin < nb)
+    for (int b = lane; b < nblocks; b += 32) s += partials[(long long)b * nb + bin];
+  for (int off = 16; off > 0; off >>= 1) s += __shfl_down(s, off, 32);
+  if (lane == 0 && bin < nb) out[bin] = s;
 }
 
 // ------------------------------------------------------------------ forcing

@@ -48,11 +48,12 @@ struct FastCfg {
 // from its L2.  The tile list is padded to a multiple of 8 with empty tiles.
 template <typename C>
 __global__ void __launch_bounds__(kFastL * C::TPL)
-f_xinv(const Cx<float>* __restrict__ S, Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg,
-       const Cx<float>* __restrict__ ph, int shifted, const int2* __restrict__ tiles, Geom g) {
+f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg,
+       Shift sh, const int2* __restrict__ tiles, Geom g) {
   constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
   using F = RegFft<N, TPL, +1, typename C::Inv>;
   __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> phx[N];
   __shared__ Cx<float> xb[N * kFastLp];
   const int tid = threadIdx.x;
   const int l = tid % kFastL, t = tid / kFastL;
@@ -64,9 +65,13 @@ f_xinv(const Cx<float>* __restrict__ S, Cx<float>* __restrict__ W, const Cx<floa
   for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
   const bool col = kz < g.kzn;
   Cx<float> phyz = cx(1.f, 0.f);
-  if (shifted && col) phyz = cmul(ph[N + yi], ph[2 * N + kz]);
+  if (sh.on) {
+    phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
+    if (col) phyz = cmul(phase1<float>(ky, sh.s[1], N), phase1<float>(kz, sh.s[2], N));
+    __syncthreads();
+  }
   const LineView<float, kFastLp> lv{xb + l};
-  const long long sbase = (long long)yi * g.h + kz;
+  const long long sbase = (long long)yi * ls.pitch + kz;
   // field f = sum_c coef_c(k) u_c: u_x, u_y, u_z, then omega = i k x u
   const int c1 = (f < 3) ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
   const int c2 = (f == 3) ? 1 : (f == 4 ? 2 : 0);
@@ -78,19 +83,19 @@ f_xinv(const Cx<float>* __restrict__ S, Cx<float>* __restrict__ W, const Cx<floa
     const int kx = kval(p, N);
     Cx<float> val = cx(0.f, 0.f);
     if (col && retained(g, kx, ky, kz)) {
-      const long long idx = (long long)p * N * g.h + sbase;
-      const Cx<float> a1 = S[c1 * g.comp + idx];
+      const long long idx = (long long)p * N * ls.pitch + sbase;
+      const Cx<float> a1 = S[c1 * ls.cs + idx];
       if (f < 3) {
         val = a1;
       } else {
-        const Cx<float> a2 = S[c2 * g.comp + idx];
+        const Cx<float> a2 = S[c2 * ls.cs + idx];
         const float kxf = float(kx);
         // omega_x = i(ky u_z - kz u_y), omega_y = i(kz u_x - kx u_z), omega_z = i(kx u_y - ky u_x)
         const float w1 = (f == 3) ? kyf : (f == 4 ? kzf : kxf);
         const float w2 = (f == 3) ? kzf : (f == 4 ? kxf : kyf);
         val = mul_i(scale(a1, w1) - scale(a2, w2));
       }
-      if (shifted) val = cmul(val, cmul(ph[p], phyz));
+      if (sh.on) val = cmul(val, cmul(phx[p], phyz));
     }
     v[i] = val;
   }
@@ -150,14 +155,15 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   using FI = RegFft<N, TPL, +1, typename C::Inv>;
   using FF = RegFft<N, TPL, -1, typename C::Fwd>;
   static_assert(FI::RL == FF::R0, "the forward transform must start with the last inverse radix");
+  constexpr int LP = line_pitch(N);
   __shared__ Cx<float> tw[N];
-  __shared__ Cx<float> xb[P * (N + 1)];  // exchanges, then the spectrum of f_z
-  __shared__ Cx<float> sp[P * N];        // spectrum of f_x + i f_y
+  __shared__ Cx<float> xb[P * LP];  // exchanges, then the spectrum of f_z
+  __shared__ Cx<float> sp[P * N];   // spectrum of f_x + i f_y
   const int tid = threadIdx.x;
   const int p = tid / TPL, t = tid % TPL;
   const long long line = (long long)blockIdx.x * P + p;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
-  const LineView<float, 1> lv{xb + p * (N + 1)};
+  const LineView<float, 1> lv{xb + p * LP};
   const Cx<float>* src = W + line * g.kzp;
   float fx[EPT], fy[EPT], fz[EPT];
   Cx<float> z[2][EPT];
@@ -201,7 +207,7 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   FF::run(v, t, lv, tw);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) xb[p * (N + 1) + FF::out_pos(t, i)] = v[i];
+  for (int i = 0; i < EPT; ++i) xb[p * LP + FF::out_pos(t, i)] = v[i];
   __syncthreads();
   const long long line0 = (long long)blockIdx.x * P;
   for (int idx = tid; idx < P * g.kzn; idx += NT) {
@@ -210,18 +216,19 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
     const long long off = (line0 + pp) * g.kzp + k;
     W[off] = cx(0.5f * (c1.re + c2.re), 0.5f * (c1.im - c2.im));
     W[g.wcomp + off] = cx(0.5f * (c1.im + c2.im), -0.5f * (c1.re - c2.re));
-    W[2 * g.wcomp + off] = xb[pp * (N + 1) + k];
+    W[2 * g.wcomp + off] = xb[pp * LP + k];
   }
 }
 
 // ------------------------------------------------------------------ x forward + epilogue
 template <typename C, int OP>
 __global__ void __launch_bounds__(kFastL * C::TPL)
-f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, const Cx<float>* __restrict__ ph,
-       int shifted, const int2* __restrict__ tiles, Geom g, EpiArgs<float> a) {
+f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh,
+       const int2* __restrict__ tiles, Geom g, EpiArgs<float> a) {
   constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
   using F = RegFft<N, TPL, -1, typename C::Fwd>;
   __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> phx[N];
   __shared__ Cx<float> xb[N * kFastLp];
   const int tid = threadIdx.x;
   const int l = tid % kFastL, t = tid / kFastL;
@@ -241,6 +248,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, const
   Cx<float> r[3][EPT];
   if (active) {
     for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
+    if (sh.on) phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
     const bool col = kz < g.kzn;
     const Cx<float>* src = W + (long long)yi * g.kzp + kz;
 #pragma unroll
@@ -254,24 +262,25 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, const
   if (kz >= g.h || (!a.full && kz >= g.kzn)) return;
   const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
   Cx<float> phyz = cx(1.f, 0.f);
-  if (shifted && active && kz < g.kzn) phyz = cmul(ph[N + yi], ph[2 * N + kz]);
+  if (sh.on && active && kz < g.kzn) phyz = cmul(phase1<float>(ky, sh.s[1], N), phase1<float>(kz, sh.s[2], N));
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::out_pos(t, i);
     const int kx = kval(p, N);
-    const long long idx = ((long long)p * N + yi) * g.h + kz;
+    const long long io0 = lay_at(a.lo0, p, yi, kz, N);
     const bool ret = active && kz < g.kzn && retained(g, kx, ky, kz);
     if (!ret) {
-      for (int c = 0; c < 3; ++c) {
-        a.out0[c * g.comp + idx] = cx(0.f, 0.f);
-        if (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2)
-          a.out1[c * g.comp + idx] = cx(0.f, 0.f);
-      }
+      // outside the retained set: zero in outputs that must be complete (full
+      // mode, the caller's arrays); stage buffers are only read at retained modes
+      if (a.full)
+        for (int c = 0; c < 3; ++c) a.out0[c * a.lo0.cs + io0] = cx(0.f, 0.f);
       continue;
     }
+    const long long io1 = lay_at(a.lo1, p, yi, kz, N);
+    const long long ii0 = lay_at(a.li0, p, yi, kz, N), ii1 = lay_at(a.li1, p, yi, kz, N);
     Cx<float> Fv[3] = {scale(r[0][i], inv_n3), scale(r[1][i], inv_n3), scale(r[2][i], inv_n3)};
-    if (shifted) {
-      const Cx<float> phi = cmul(ph[p], phyz);
+    if (sh.on) {
+      const Cx<float> phi = cmul(phx[p], phyz);
       Fv[0] = cmulc(Fv[0], phi);
       Fv[1] = cmulc(Fv[1], phi);
       Fv[2] = cmulc(Fv[2], phi);
@@ -292,38 +301,39 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, const
     const float dt = a.dt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const long long o = c * g.comp + idx;
+      const long long o0 = c * a.lo0.cs + io0, o1 = c * a.lo1.cs + io1;
+      const long long i0 = c * a.li0.cs + ii0, i1 = c * a.li1.cs + ii1;
       const Cx<float> Nv = Fv[c];
       if (OP == OP_STORE) {
-        a.out0[o] = Nv;
+        a.out0[o0] = Nv;
       } else if (OP == OP_AVG) {
-        a.out0[o] = scale(a.in1[o] + Nv, 0.5f);
+        a.out0[o0] = scale(a.in1[i1] + Nv, 0.5f);
       } else if (OP == OP_HEUN1) {
         Cx<float> O = cx(0.f, 0.f);
         if (a.force != nullptr && k2 >= 4 && k2 <= 9) O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
-        const Cx<float> s0 = a.in0[o];
-        a.out1[o] = scale(s0 + scale(Nv + O, dt), edt);
-        a.out0[o] = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
+        const Cx<float> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0 + scale(Nv + O, dt), edt);
+        a.out0[o0] = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
       } else if (OP == OP_HEUN2) {
-        a.out0[o] = a.in1[o] + scale(Nv, 0.5f * dt * eh);
+        a.out0[o0] = a.in1[i1] + scale(Nv, 0.5f * dt * eh);
       } else if (OP == OP_EX1B) {
-        a.out0[o] = scale(a.in0[o] + scale(a.in1[o] + Nv, 0.25f * dt), eh);
+        a.out0[o0] = scale(a.in0[i0] + scale(a.in1[i1] + Nv, 0.25f * dt), eh);
       } else if (OP == OP_EX2B) {
-        a.out0[o] = scale(a.in0[o], edt) + scale(a.in1[o] + Nv, 0.5f * dt * eh);
+        a.out0[o0] = scale(a.in0[i0], edt) + scale(a.in1[i1] + Nv, 0.5f * dt * eh);
       } else if (OP == OP_RK4_0) {
-        const Cx<float> s0 = a.in0[o];
-        a.out1[o] = scale(s0 + scale(Nv, 0.5f * dt), eh);
-        a.out0[o] = scale(s0 + scale(Nv, dt / 6.f), edt);
+        const Cx<float> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0 + scale(Nv, 0.5f * dt), eh);
+        a.out0[o0] = scale(s0 + scale(Nv, dt / 6.f), edt);
       } else if (OP == OP_RK4_1) {
-        const Cx<float> s0 = a.in0[o];
-        a.out1[o] = scale(s0, eh) + scale(Nv, 0.5f * dt);
-        a.out0[o] = a.in1[o] + scale(Nv, dt / 3.f * eh);
+        const Cx<float> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0, eh) + scale(Nv, 0.5f * dt);
+        a.out0[o0] = a.in1[i1] + scale(Nv, dt / 3.f * eh);
       } else if (OP == OP_RK4_2) {
-        const Cx<float> s0 = a.in0[o];
-        a.out1[o] = scale(s0, edt) + scale(Nv, dt * eh);
-        a.out0[o] = a.in1[o] + scale(Nv, dt / 3.f * eh);
+        const Cx<float> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0, edt) + scale(Nv, dt * eh);
+        a.out0[o0] = a.in1[i1] + scale(Nv, dt / 3.f * eh);
       } else {
-        a.out0[o] = a.in1[o] + scale(Nv, dt / 6.f);
+        a.out0[o0] = a.in1[i1] + scale(Nv, dt / 6.f);
       }
     }
   }

@@ -75,7 +75,7 @@ struct Layout {
   int nsh, nbins;
   std::vector<int2> tiles;   // active (k_y index, k_z tile start), padded to a multiple of 8
   int ntiles_active;
-  size_t off_tw, off_ph, off_etab, off_force, off_tiles, off_w, off_s, off_a, off_spec, off_specout;
+  size_t off_tw, off_etab, off_force, off_tiles, off_w, off_s, off_a, off_spec, off_specout;
   size_t total;
 };
 
@@ -200,13 +200,12 @@ bool make_layout(const ns_config* c, Layout* lay) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, kAlign); return o; };
   lay->off_tw = take(n * e);
-  lay->off_ph = take((2 * n + g.h) * e);
   lay->off_etab = take(2 * (size_t)(lay->k2top + 1) * rsz);
   lay->off_force = take(3 * 196 * e);
   lay->off_tiles = take(lay->tiles.size() * sizeof(int2) + 8);
   lay->off_w = take(9 * (size_t)g.wcomp * e);
-  lay->off_s = take(3 * (size_t)g.comp * e);
-  lay->off_a = take(3 * (size_t)g.comp * e);
+  lay->off_s = take(3 * (size_t)g.wcomp * e);   // stage buffers in the compact layout
+  lay->off_a = take(3 * (size_t)g.wcomp * e);
   lay->off_spec = take((size_t)kSpecBlocks * lay->nbins * sizeof(double));
   lay->off_specout = take((size_t)lay->nbins * sizeof(double));
   lay->total = off;
@@ -223,6 +222,7 @@ struct ns_ctx {
   std::string err;
   std::vector<double> host_spec;
   int fast = 0;       // N of the specialised FP32 passes in use (0: generic passes)
+  double etab_dt = -1.0;  // dt of the integrating-factor tables now in the workspace
   // per-pass timing: events[2 i], events[2 i + 1] bracket launch i of pass tpass[i]
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -274,7 +274,6 @@ hipError_t tstop(ns_ctx* c) {
 template <typename R>
 struct Ptrs {
   Cx<R>* tw;
-  Cx<R>* ph;
   R* eh;
   R* edt;
   Cx<R>* force;
@@ -291,7 +290,6 @@ Ptrs<R> ptrs(ns_ctx* c) {
   const Layout& l = c->lay;
   Ptrs<R> p;
   p.tw = reinterpret_cast<Cx<R>*>(c->ws + l.off_tw);
-  p.ph = reinterpret_cast<Cx<R>*>(c->ws + l.off_ph);
   p.eh = reinterpret_cast<R*>(c->ws + l.off_etab);
   p.edt = p.eh + (l.k2top + 1);
   p.force = reinterpret_cast<Cx<R>*>(c->ws + l.off_force);
@@ -304,7 +302,19 @@ Ptrs<R> ptrs(ns_ctx* c) {
   return p;
 }
 
-size_t lds_strided(const Layout& l) { return (size_t)(l.g.n + l.g.n * l.g.L) * l.elem; }
+size_t lds_strided(const Layout& l) { return (size_t)(2 * l.g.n + l.g.n * l.g.L) * l.elem; }
+
+// Layouts: the caller's arrays and the compact internal stage buffers.
+ns::Lay user_lay(const Layout& l) { return ns::Lay{l.g.h, l.g.comp}; }
+ns::Lay compact_lay(const Layout& l) { return ns::Lay{l.g.kzp, l.g.wcomp}; }
+ns::Shift make_shift(const double* s) {
+  ns::Shift sh;
+  sh.s[0] = s ? s[0] : 0.0;
+  sh.s[1] = s ? s[1] : 0.0;
+  sh.s[2] = s ? s[2] : 0.0;
+  sh.on = (s != nullptr && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0)) ? 1 : 0;
+  return sh;
+}
 size_t lds_z(const Layout& l) { return (size_t)(l.g.n + 3 * l.pz * l.g.n) * l.elem; }
 size_t lds_zadj(const Layout& l) { return (size_t)(l.g.n + (9 * l.pa * l.g.n) / 2) * l.elem; }
 
@@ -316,7 +326,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename R, int OP>
-hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, int shifted, const EpiArgs<R>& a) {
+hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, const ns::Shift& sh, const EpiArgs<R>& a) {
   const Layout& l = c->lay;
   const size_t lds = lds_strided(l);
   auto kern = ns::k_xfwd<R, kEpt, OP>;
@@ -324,14 +334,13 @@ hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, int shifted, const EpiArgs<R
   if (e != hipSuccess) return e;
   const int nblk = a.full ? l.g.n * l.ntzf : l.ntiles_active;
   if (nblk == 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, p.ph, shifted,
-                     p.tiles, l.g, l.plan, a);
+  hipLaunchKernelGGL(kern, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, sh, p.tiles, l.g, l.plan, a);
   return hipGetLastError();
 }
 
 // Specialised FP32 passes for one compile-time size (same semantics and layout).
 template <typename C, int OP>
-ns_status eval_fast(ns_ctx* c, const Cx<float>* in, int shifted, const EpiArgs<float>& a) {
+ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift& sh, const EpiArgs<float>& a) {
   const Layout& l = c->lay;
   const Geom& g = l.g;
   Ptrs<float> p = ptrs<float>(c);
@@ -342,7 +351,7 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, int shifted, const EpiArgs<f
     const int padded = (ntiles + 7) / 8 * 8;
     if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(6 * padded), dim3(ns::kFastL * C::XInv::TPL), 0,
-                       c->stream, in, p.W, p.tw, p.ph, shifted, p.tiles, g);
+                       c->stream, in, lin, p.W, p.tw, sh, p.tiles, g);
     if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
@@ -361,31 +370,27 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, int shifted, const EpiArgs<f
   if ((e = tstart(c, 4)) != hipSuccess) return hip_check(c, e, "timing event");
   if (nblk > 0)
     hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
-                       c->stream, p.W, p.tw, p.ph, shifted, p.tiles, g, a);
+                       c->stream, p.W, p.tw, sh, p.tiles, g, a);
   if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   return hip_check(c, hipGetLastError(), "nonlinear-term launch");
 }
 
-// One evaluation of the nonlinear term on the state-layout array `in` with the
-// shift s (NULL or all zero = unshifted); the x-forward epilogue applies OP.
+// One evaluation of the nonlinear term on `in` (layout lin) with the shift s (NULL
+// or all zero = unshifted); the x-forward epilogue applies OP with the operands
+// and layouts in a.
 template <typename R, int OP>
-ns_status eval(ns_ctx* c, const Cx<R>* in, const double* s, EpiArgs<R> a) {
+ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs<R> a) {
   const Layout& l = c->lay;
   const Geom& g = l.g;
   Ptrs<R> p = ptrs<R>(c);
-  const int shifted = (s != nullptr && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0)) ? 1 : 0;
+  const ns::Shift sh = make_shift(s);
   hipError_t e;
-  if (shifted) {
-    const int nt = 2 * g.n + g.h;
-    hipLaunchKernelGGL(ns::k_phase<R>, dim3((nt + 255) / 256), dim3(256), 0, c->stream, p.ph, g.n,
-                       g.h, s[0], s[1], s[2]);
-  }
   if constexpr (std::is_same<R, float>::value) {
     switch (c->fast) {
-      case 64: return eval_fast<ns::Fast64, OP>(c, in, shifted, a);
-      case 128: return eval_fast<ns::Fast128, OP>(c, in, shifted, a);
-      case 192: return eval_fast<ns::Fast192, OP>(c, in, shifted, a);
-      case 256: return eval_fast<ns::Fast256, OP>(c, in, shifted, a);
+      case 64: return eval_fast<ns::Fast64, OP>(c, in, lin, sh, a);
+      case 128: return eval_fast<ns::Fast128, OP>(c, in, lin, sh, a);
+      case 192: return eval_fast<ns::Fast192, OP>(c, in, lin, sh, a);
+      case 256: return eval_fast<ns::Fast256, OP>(c, in, lin, sh, a);
       default: break;
     }
   }
@@ -395,8 +400,7 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, const double* s, EpiArgs<R> a) {
     auto k1 = ns::k_xinv<R, kEpt>;
     if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
     if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, in, p.W, p.tw, p.ph, shifted,
-                       p.tiles, g, l.plan);
+    hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, in, lin, p.W, p.tw, sh, p.tiles, g, l.plan);
     if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     auto k2 = ns::k_ypass<R, kEpt, +1>;
     if ((e = allow_lds(k2, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
@@ -419,11 +423,12 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, const double* s, EpiArgs<R> a) {
     if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   }
   if ((e = tstart(c, 4)) != hipSuccess) return hip_check(c, e, "timing event");
-  if ((e = launch_xfwd<R, OP>(c, p, shifted, a)) != hipSuccess) return hip_check(c, e, "k_xfwd launch");
+  if ((e = launch_xfwd<R, OP>(c, p, sh, a)) != hipSuccess) return hip_check(c, e, "k_xfwd launch");
   if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   return hip_check(c, hipGetLastError(), "nonlinear-term launch");
 }
 
+// Epilogue operands; every layout defaults to the compact internal one.
 template <typename R>
 EpiArgs<R> epi(ns_ctx* c, int full) {
   EpiArgs<R> a;
@@ -433,6 +438,7 @@ EpiArgs<R> epi(ns_ctx* c, int full) {
   a.edt = p.edt;
   a.full = full;
   a.ntzf = c->lay.ntzf;
+  a.lo0 = a.lo1 = a.li0 = a.li1 = compact_lay(c->lay);
   return a;
 }
 
@@ -440,48 +446,57 @@ template <typename R>
 ns_status nonlinear_t(ns_ctx* c, const void* u, void* nh, const double* shift, int flags) {
   const Cx<R>* in = static_cast<const Cx<R>*>(u);
   Cx<R>* out = static_cast<Cx<R>*>(nh);
+  const ns::Lay U = user_lay(c->lay);
   EpiArgs<R> a = epi<R>(c, 1);
   a.out0 = out;
+  a.lo0 = a.li1 = U;
   if (flags & NS_NL_PS_AVG) {
     const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
-    ns_status st = eval<R, ns::OP_STORE>(c, in, zero, a);
+    ns_status st = eval<R, ns::OP_STORE>(c, in, U, zero, a);
     if (st != NS_OK) return st;
     a.in1 = out;
-    return eval<R, ns::OP_AVG>(c, in, half, a);
+    return eval<R, ns::OP_AVG>(c, in, U, half, a);
   }
-  return eval<R, ns::OP_STORE>(c, in, shift, a);
+  return eval<R, ns::OP_STORE>(c, in, U, shift, a);
 }
 
+// exp(-nu k^2 dt/2) and exp(-nu k^2 dt) tables; kept while dt does not change.
 template <typename R>
 ns_status etab(ns_ctx* c, double dt) {
+  if (c->etab_dt == dt) return NS_OK;
   Ptrs<R> p = ptrs<R>(c);
   const long long nt = c->lay.k2top + 1;
   hipLaunchKernelGGL(ns::k_etab<R>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, p.eh,
                      p.edt, c->lay.k2top, c->cfg.nu, dt);
-  return hip_check(c, hipGetLastError(), "k_etab launch");
+  ns_status st = hip_check(c, hipGetLastError(), "k_etab launch");
+  if (st == NS_OK) c->etab_dt = dt;
+  return st;
 }
 
 template <typename R>
 ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
   Cx<R>* s0 = static_cast<Cx<R>*>(u);
   Ptrs<R> p = ptrs<R>(c);
+  const ns::Lay U = user_lay(c->lay), K = compact_lay(c->lay);
   ns_status st = etab<R>(c, dt);
   if (st != NS_OK) return st;
   for (int i = 0; i < nsteps; ++i) {
     EpiArgs<R> a = epi<R>(c, 0);
     a.dt = R(dt);
     a.in0 = s0;
+    a.li0 = U;
     a.in1 = p.ab;
     a.out0 = p.ab;
     a.out1 = p.sb;
-    if ((st = eval<R, ns::OP_RK4_0>(c, s0, nullptr, a)) != NS_OK) return st;
-    if ((st = eval<R, ns::OP_RK4_1>(c, p.sb, nullptr, a)) != NS_OK) return st;
-    if ((st = eval<R, ns::OP_RK4_2>(c, p.sb, nullptr, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_RK4_0>(c, s0, U, nullptr, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_RK4_1>(c, p.sb, K, nullptr, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_RK4_2>(c, p.sb, K, nullptr, a)) != NS_OK) return st;
     EpiArgs<R> f = epi<R>(c, 1);
     f.dt = R(dt);
     f.in1 = p.ab;
     f.out0 = s0;
-    if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, nullptr, f)) != NS_OK) return st;
+    f.lo0 = U;
+    if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, K, nullptr, f)) != NS_OK) return st;
   }
   return NS_OK;
 }
@@ -503,6 +518,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
                const ns_forcing* fo, long long step0) {
   Cx<R>* s0 = static_cast<Cx<R>*>(u);
   Ptrs<R> p = ptrs<R>(c);
+  const ns::Lay U = user_lay(c->lay), K = compact_lay(c->lay);
   ns_status st = etab<R>(c, dt);
   if (st != NS_OK) return st;
   const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
@@ -511,19 +527,22 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
       EpiArgs<R> a = epi<R>(c, 0);
       a.dt = R(dt);
       a.out0 = p.ab;
-      if ((st = eval<R, ns::OP_STORE>(c, s0, zero, a)) != NS_OK) return st;
+      if ((st = eval<R, ns::OP_STORE>(c, s0, U, zero, a)) != NS_OK) return st;
       a.in0 = s0;
+      a.li0 = U;
       a.in1 = p.ab;
       a.out0 = p.sb;
-      if ((st = eval<R, ns::OP_EX1B>(c, s0, half, a)) != NS_OK) return st;
+      if ((st = eval<R, ns::OP_EX1B>(c, s0, U, half, a)) != NS_OK) return st;
       a.out0 = p.ab;
-      if ((st = eval<R, ns::OP_STORE>(c, p.sb, zero, a)) != NS_OK) return st;
+      if ((st = eval<R, ns::OP_STORE>(c, p.sb, K, zero, a)) != NS_OK) return st;
       EpiArgs<R> f = epi<R>(c, 1);
       f.dt = R(dt);
       f.in0 = s0;
+      f.li0 = U;
       f.in1 = p.ab;
       f.out0 = s0;
-      if ((st = eval<R, ns::OP_EX2B>(c, p.sb, half, f)) != NS_OK) return st;
+      f.lo0 = U;
+      if ((st = eval<R, ns::OP_EX2B>(c, p.sb, K, half, f)) != NS_OK) return st;
       continue;
     }
     double al[3] = {0, 0, 0};
@@ -536,6 +555,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     EpiArgs<R> a = epi<R>(c, 0);
     a.dt = R(dt);
     a.in0 = s0;
+    a.li0 = U;
     a.out0 = p.ab;
     a.out1 = p.sb;
     if (fo != nullptr) {
@@ -545,41 +565,36 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
       if ((st = hip_check(c, hipGetLastError(), "k_forcing launch")) != NS_OK) return st;
       a.force = p.force;
     }
-    if ((st = eval<R, ns::OP_HEUN1>(c, s0, al, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_HEUN1>(c, s0, U, al, a)) != NS_OK) return st;
     EpiArgs<R> f = epi<R>(c, 1);
     f.dt = R(dt);
     f.in1 = p.ab;
     f.out0 = s0;
-    if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, be, f)) != NS_OK) return st;
+    f.lo0 = U;
+    if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f)) != NS_OK) return st;
   }
   return NS_OK;
 }
 
-// One transposed linearised evaluation at state `st` with shift s: lam-pass input
-// from `la`, adjoint stage combination AOP in the last pass.
+// One transposed linearised evaluation at state `st` (layout lst) with shift s:
+// lam-pass input from `la`, adjoint stage combination AOP in the last pass.
 template <typename R, int AOP>
-ns_status adj_eval(ns_ctx* c, const Cx<R>* st, const double* s, const LamArgs<R>& la, AdjArgs<R> aa) {
+ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, const LamArgs<R>& la,
+                   AdjArgs<R> aa) {
   const Layout& l = c->lay;
   const Geom& g = l.g;
   Ptrs<R> p = ptrs<R>(c);
-  const int shifted = (s != nullptr && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0)) ? 1 : 0;
+  const ns::Shift sh = make_shift(s);
   hipError_t e;
-  if (shifted) {
-    const int nt = 2 * g.n + g.h;
-    hipLaunchKernelGGL(ns::k_phase<R>, dim3((nt + 255) / 256), dim3(256), 0, c->stream, p.ph, g.n,
-                       g.h, s[0], s[1], s[2]);
-  }
   const size_t lds = lds_strided(l);
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
     auto k1 = ns::k_xinv<R, kEpt>;
     if ((e = allow_lds(k1, lds)) != hipSuccess) return hip_check(c, e, "k_xinv attribute");
-    hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, st, p.W, p.tw, p.ph, shifted,
-                       p.tiles, g, l.plan);
+    hipLaunchKernelGGL(k1, dim3(ntiles), dim3(l.tx), lds, c->stream, st, lst, p.W, p.tw, sh, p.tiles, g, l.plan);
     auto kl = ns::k_xlam<R, kEpt>;
     if ((e = allow_lds(kl, lds)) != hipSuccess) return hip_check(c, e, "k_xlam attribute");
-    hipLaunchKernelGGL(kl, dim3(ntiles), dim3(l.tx), lds, c->stream, la, p.W, p.tw, p.ph, shifted,
-                       p.tiles, g, l.plan);
+    hipLaunchKernelGGL(kl, dim3(ntiles), dim3(l.tx), lds, c->stream, la, p.W, p.tw, sh, p.tiles, g, l.plan);
     auto k2 = ns::k_ypass<R, kEpt, +1>;
     if ((e = allow_lds(k2, lds)) != hipSuccess) return hip_check(c, e, "k_ypass attribute");
     hipLaunchKernelGGL(k2, dim3(9 * g.n * l.ntz), dim3(l.tx), lds, c->stream, p.W, p.tw, 0, l.ntz, g,
@@ -599,8 +614,7 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, const double* s, const LamArgs<R>
   const int nblk = aa.full ? g.n * l.ntzf : ntiles;
   aa.ntzf = l.ntzf;
   if (nblk > 0)
-    hipLaunchKernelGGL(k5, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, p.ph, shifted, p.tiles, g,
-                       l.plan, aa);
+    hipLaunchKernelGGL(k5, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, sh, p.tiles, g, l.plan, aa);
   return hip_check(c, hipGetLastError(), "adjoint launch");
 }
 
@@ -609,6 +623,7 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
   const Cx<R>* u0 = static_cast<const Cx<R>*>(u0v);
   Cx<R>* lam = static_cast<Cx<R>*>(lamv);
   Ptrs<R> p = ptrs<R>(c);
+  const ns::Lay U = user_lay(c->lay), K = compact_lay(c->lay);
   ns_status st = etab<R>(c, dt);
   if (st != NS_OK) return st;
   const R rdt = R(dt);
@@ -618,11 +633,14 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
     a.eh = p.eh;
     a.edt = p.edt;
     a.full = full;
+    a.lo0 = a.li0 = a.li1 = K;
     return a;
   };
-  auto lamargs = [&](const Cx<R>* A, R cA, const R* eA, const Cx<R>* B, R cB, const R* eB) {
+  auto lamargs = [&](const Cx<R>* A, ns::Lay LA, R cA, const R* eA, const Cx<R>* B, R cB, const R* eB) {
     LamArgs<R> la;
     la.A = A; la.B = B; la.eA = eA; la.eB = eB; la.cA = cA; la.cB = cB;
+    la.la = LA;
+    la.lb = K;
     return la;
   };
   const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
@@ -630,26 +648,31 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
     EpiArgs<R> f = epi<R>(c, 0);
     f.dt = rdt;
     f.out0 = p.ab;
-    if ((st = eval<R, ns::OP_STORE>(c, u0, zero, f)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_STORE>(c, u0, U, zero, f)) != NS_OK) return st;
     f.in0 = u0;
+    f.li0 = U;
     f.in1 = p.ab;
     f.out0 = p.sb;
-    if ((st = eval<R, ns::OP_EX1B>(c, u0, half, f)) != NS_OK) return st;  // sb = S_h
-    LamArgs<R> l1 = lamargs(lam, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
+    if ((st = eval<R, ns::OP_EX1B>(c, u0, U, half, f)) != NS_OK) return st;  // sb = S_h
+    LamArgs<R> l1 = lamargs(lam, U, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
     AdjArgs<R> a = adj(0);
     a.out0 = p.ab;
-    if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, zero, l1, a)) != NS_OK) return st;
+    if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, K, zero, l1, a)) != NS_OK) return st;
     a.in1 = p.ab;
-    if ((st = adj_eval<R, ns::AOP_ACC>(c, p.sb, half, l1, a)) != NS_OK) return st;  // ab = mu
-    LamArgs<R> l2 = lamargs(p.ab, R(0.25) * rdt, p.eh, nullptr, R(0), nullptr);
+    if ((st = adj_eval<R, ns::AOP_ACC>(c, p.sb, K, half, l1, a)) != NS_OK) return st;  // ab = mu
+    LamArgs<R> l2 = lamargs(p.ab, K, R(0.25) * rdt, p.eh, nullptr, R(0), nullptr);
     a.in0 = lam;
+    a.li0 = U;
     a.in1 = p.ab;
     a.out0 = lam;
-    if ((st = adj_eval<R, ns::AOP_EXACT>(c, u0, zero, l2, a)) != NS_OK) return st;
+    a.lo0 = U;
+    if ((st = adj_eval<R, ns::AOP_EXACT>(c, u0, U, zero, l2, a)) != NS_OK) return st;
     AdjArgs<R> b = adj(1);
     b.in1 = lam;
+    b.li1 = U;
     b.out0 = lam;
-    return adj_eval<R, ns::AOP_ACC>(c, u0, half, l2, b);
+    b.lo0 = U;
+    return adj_eval<R, ns::AOP_ACC>(c, u0, U, half, l2, b);
   }
   double al[3] = {0, 0, 0};
   if (variant == NS_PS_RANDOM)
@@ -659,19 +682,22 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
   EpiArgs<R> f = epi<R>(c, 0);
   f.dt = rdt;
   f.in0 = u0;
+  f.li0 = U;
   f.out0 = p.ab;
   f.out1 = p.sb;
-  if ((st = eval<R, ns::OP_HEUN1>(c, u0, al, f)) != NS_OK) return st;  // sb = S1
-  LamArgs<R> l1 = lamargs(lam, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
+  if ((st = eval<R, ns::OP_HEUN1>(c, u0, U, al, f)) != NS_OK) return st;  // sb = S1
+  LamArgs<R> l1 = lamargs(lam, U, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
   AdjArgs<R> a = adj(0);
   a.out0 = p.ab;
-  if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, be, l1, a)) != NS_OK) return st;  // ab = mu1
-  LamArgs<R> l2 = lamargs(lam, R(0.5) * rdt, p.eh, p.ab, rdt, p.edt);
+  if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, K, be, l1, a)) != NS_OK) return st;  // ab = mu1
+  LamArgs<R> l2 = lamargs(lam, U, R(0.5) * rdt, p.eh, p.ab, rdt, p.edt);
   AdjArgs<R> b = adj(1);
   b.in0 = lam;
+  b.li0 = U;
   b.in1 = p.ab;
   b.out0 = lam;
-  return adj_eval<R, ns::AOP_HEUN>(c, u0, al, l2, b);
+  b.lo0 = U;
+  return adj_eval<R, ns::AOP_HEUN>(c, u0, U, al, l2, b);
 }
 
 template <typename R>
@@ -684,7 +710,7 @@ ns_status spectra_t(ns_ctx* c, const void* u, const void* nh, ns_spectra_out* ou
   hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(256), lds, c->stream,
                      static_cast<const Cx<R>*>(u), static_cast<const Cx<R>*>(nh), c->cfg.nu, l.g.n,
                      l.g.h, l.nsh, l.g.comp, p.spec);
-  hipLaunchKernelGGL(ns::k_spectra_sum, dim3((l.nbins + 255) / 256), dim3(256), 0, c->stream, p.spec,
+  hipLaunchKernelGGL(ns::k_spectra_sum, dim3((l.nbins + 7) / 8), dim3(256), 0, c->stream, p.spec,
                      kSpecBlocks, l.nbins, p.specout);
   ns_status st = hip_check(c, hipGetLastError(), "spectra launch");
   if (st != NS_OK) return st;

@@ -3,7 +3,8 @@
 // the integrating-factor Runge-Kutta stage updates fused behind it.
 //
 // Five launches per evaluation, all bandwidth-bound:
-//   k_xinv   state -> scratch: phase shift, curl, inverse FFT along x (6 fields)
+//   k_xinv   state -> scratch: phase shift, curl, inverse FFT along x (6 fields);
+//            the shift factors are generated per block in FP64 and rounded once
 //   k_ypass  scratch in place: inverse FFT along y (6 fields)
 //   k_zcross scratch in place: c2r along z (6 fields), u x omega, r2c along z (3 fields)
 //   k_ypass  scratch in place: forward FFT along y (3 fields)
@@ -61,18 +62,47 @@ __device__ __forceinline__ bool line_active(const Geom& g, int ky, int kz) {
 template <typename R>
 __device__ __forceinline__ Cx<R> mul_i(Cx<R> a) { return cx(-a.im, a.re); }
 
+// Addressing of a state-shaped array: the caller's layout [3][N][N][N/2+1]
+// (pitch N/2+1) or the compact internal one [3][N][N][kzp] (k_z < kzn only,
+// rows aligned to the tile width).
+struct Lay {
+  int pitch;        // k_z pitch of a (k_x, k_y) row
+  long long cs;     // component stride
+};
+__device__ __forceinline__ long long lay_at(const Lay& L, int xi, int yi, int kz, int n) {
+  return ((long long)xi * n + yi) * L.pitch + kz;
+}
+
+// Grid shift s (grid-spacing units); on == 0: unshifted.
+struct Shift {
+  double s[3];
+  int on;
+};
+// exp(2 pi i k s / N), evaluated in FP64 (sincospi) and rounded once.
+template <typename R>
+__device__ __forceinline__ Cx<R> phase1(int k, double s, int n) {
+  double sn, cs;
+  sincospi(2.0 * (double)k * s / (double)n, &sn, &cs);
+  return cx(R(cs), R(sn));
+}
+// Per-block table of the k_x factors: ph[i] = exp(2 pi i kval(i) s_x / N).
+template <typename R>
+__device__ __forceinline__ void phase_row(Cx<R>* ph, int n, double s, int tid, int nt) {
+  for (int i = tid; i < n; i += nt) ph[i] = phase1<R>(kval(i, n), s, n);
+}
+
 // ------------------------------------------------------------------ k_xinv
 // One block per active (k_y, k_z tile); points p = k_x index, columns l = k_z - kz0.
 // Holds the three velocity components in registers and sends the six fields
 // u_x, u_y, u_z, omega_x, omega_y, omega_z one after the other through LDS.
 template <typename R, int EPT>
 __global__ void __launch_bounds__(512)
-k_xinv(const Cx<R>* __restrict__ S, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg,
-       const Cx<R>* __restrict__ ph, int shifted, const int2* __restrict__ tiles, Geom g,
-       FftPlan plan) {
+k_xinv(const Cx<R>* __restrict__ S, Lay ls, Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg,
+       Shift sh, const int2* __restrict__ tiles, Geom g, FftPlan plan) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem_raw);
-  Cx<R>* buf = tw + g.n;
+  Cx<R>* phx = tw + g.n;
+  Cx<R>* buf = phx + g.n;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = g.n, L = g.L;
   const int2 tile = tiles[blockIdx.x];
@@ -80,9 +110,11 @@ k_xinv(const Cx<R>* __restrict__ S, Cx<R>* __restrict__ W, const Cx<R>* __restri
   const int ky = kval(yi, n);
   const int npts = n * L;
   for (int t = tid; t < n; t += nt) tw[t] = twg[t];
+  if (sh.on) phase_row(phx, n, sh.s[0], tid, nt);
+  __syncthreads();
+  const Cx<R> phy = sh.on ? phase1<R>(ky, sh.s[1], n) : cx(R(1), R(0));
 
   Cx<R> u[3][EPT];
-  Cx<R> phyz = cx(R(1), R(0));
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * nt;
@@ -91,13 +123,12 @@ k_xinv(const Cx<R>* __restrict__ S, Cx<R>* __restrict__ W, const Cx<R>* __restri
       const int p = e >> g.lgL, l = e & (L - 1);
       const int kz = kz0 + l, kx = kval(p, n);
       if (kz < g.kzn && retained(g, kx, ky, kz)) {
-        const long long idx = ((long long)p * n + yi) * g.h + kz;
+        const long long idx = lay_at(ls, p, yi, kz, n);
         u[0][i] = S[idx];
-        u[1][i] = S[g.comp + idx];
-        u[2][i] = S[2 * g.comp + idx];
-        if (shifted) {
-          phyz = cmul(ph[n + yi], ph[2 * n + kz]);
-          const Cx<R> phi = cmul(ph[p], phyz);
+        u[1][i] = S[ls.cs + idx];
+        u[2][i] = S[2 * ls.cs + idx];
+        if (sh.on) {
+          const Cx<R> phi = cmul(phx[p], cmul(phy, phase1<R>(kz, sh.s[2], n)));
           u[0][i] = cmul(u[0][i], phi);
           u[1][i] = cmul(u[1][i], phi);
           u[2][i] = cmul(u[2][i], phi);
@@ -291,8 +322,9 @@ template <typename R>
 struct EpiArgs {
   Cx<R>* out0;
   Cx<R>* out1;
-  const Cx<R>* in0;   // S0 (state layout)
-  const Cx<R>* in1;   // accumulator (state layout); may alias out0
+  const Cx<R>* in0;   // S0
+  const Cx<R>* in1;   // accumulator; may alias out0
+  Lay lo0, lo1, li0, li1;  // layouts of out0, out1, in0, in1
   const R* eh;        // exp(-nu k^2 dt/2) indexed by integer k^2
   const R* edt;       // exp(-nu k^2 dt)
   const Cx<R>* force; // [3][7][7][4] forcing on |k_i| <= 3, or null
@@ -303,11 +335,12 @@ struct EpiArgs {
 
 template <typename R, int EPT, int OP>
 __global__ void __launch_bounds__(512)
-k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* __restrict__ ph,
-       int shifted, const int2* __restrict__ tiles, Geom g, FftPlan plan, EpiArgs<R> a) {
+k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
+       const int2* __restrict__ tiles, Geom g, FftPlan plan, EpiArgs<R> a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem_raw);
-  Cx<R>* buf = tw + g.n;
+  Cx<R>* phx = tw + g.n;
+  Cx<R>* buf = phx + g.n;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = g.n, L = g.L;
   int yi, kz0;
@@ -325,6 +358,7 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* 
   Cx<R> r[3][EPT];
   if (active) {
     for (int t = tid; t < n; t += nt) tw[t] = twg[t];
+    if (sh.on) phase_row(phx, n, sh.s[0], tid, nt);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       if (f > 0) __syncthreads();
@@ -357,20 +391,21 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* 
     const int kz = kz0 + l;
     if (kz >= g.h || (!a.full && kz >= g.kzn)) continue;
     const int kx = kval(p, n);
-    const long long idx = ((long long)p * n + yi) * g.h + kz;
+    const long long io0 = lay_at(a.lo0, p, yi, kz, n);
     const bool ret = active && kz < g.kzn && retained(g, kx, ky, kz);
     if (!ret) {
-      const Cx<R> zero = cx(R(0), R(0));
-      for (int c = 0; c < 3; ++c) {
-        a.out0[c * g.comp + idx] = zero;
-        if (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2)
-          a.out1[c * g.comp + idx] = zero;
-      }
+      // zero outside the retained set only where the output must be complete (full
+      // mode writes the caller's arrays, which carry no second output)
+      if (a.full)
+        for (int c = 0; c < 3; ++c) a.out0[c * a.lo0.cs + io0] = cx(R(0), R(0));
       continue;
     }
+    const long long io1 = lay_at(a.lo1, p, yi, kz, n);
+    const long long ii0 = lay_at(a.li0, p, yi, kz, n);
+    const long long ii1 = lay_at(a.li1, p, yi, kz, n);
     Cx<R> F[3] = {scale(r[0][i], inv_n3), scale(r[1][i], inv_n3), scale(r[2][i], inv_n3)};
-    if (shifted) {
-      const Cx<R> phi = cmul(cmul(ph[p], ph[n + yi]), ph[2 * n + kz]);
+    if (sh.on) {
+      const Cx<R> phi = cmul(cmul(phx[p], phase1<R>(ky, sh.s[1], n)), phase1<R>(kz, sh.s[2], n));
       F[0] = cmulc(F[0], phi);
       F[1] = cmulc(F[1], phi);
       F[2] = cmulc(F[2], phi);
@@ -391,63 +426,48 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, const Cx<R>* 
     const R dt = a.dt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const long long o = c * g.comp + idx;
+      const long long o0 = c * a.lo0.cs + io0, o1 = c * a.lo1.cs + io1;
+      const long long i0 = c * a.li0.cs + ii0, i1 = c * a.li1.cs + ii1;
       const Cx<R> N = F[c];
       if (OP == OP_STORE) {
-        a.out0[o] = N;
+        a.out0[o0] = N;
       } else if (OP == OP_AVG) {
-        a.out0[o] = scale(a.in1[o] + N, R(0.5));
+        a.out0[o0] = scale(a.in1[i1] + N, R(0.5));
       } else if (OP == OP_HEUN1) {
         Cx<R> O = cx(R(0), R(0));
         if (a.force != nullptr && k2 >= 4 && k2 <= 9)
           O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
-        const Cx<R> s0 = a.in0[o];
-        a.out1[o] = scale(s0 + scale(N + O, dt), edt);
-        a.out0[o] = scale(s0, edt) + scale(N + O + O, R(0.5) * dt * eh);
+        const Cx<R> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0 + scale(N + O, dt), edt);
+        a.out0[o0] = scale(s0, edt) + scale(N + O + O, R(0.5) * dt * eh);
       } else if (OP == OP_HEUN2) {
-        a.out0[o] = a.in1[o] + scale(N, R(0.5) * dt * eh);
+        a.out0[o0] = a.in1[i1] + scale(N, R(0.5) * dt * eh);
       } else if (OP == OP_EX1B) {
-        const Cx<R> s0 = a.in0[o];
-        a.out0[o] = scale(s0 + scale(a.in1[o] + N, R(0.25) * dt), eh);
+        const Cx<R> s0 = a.in0[i0];
+        a.out0[o0] = scale(s0 + scale(a.in1[i1] + N, R(0.25) * dt), eh);
       } else if (OP == OP_EX2B) {
-        const Cx<R> s0 = a.in0[o];
-        a.out0[o] = scale(s0, edt) + scale(a.in1[o] + N, R(0.5) * dt * eh);
+        const Cx<R> s0 = a.in0[i0];
+        a.out0[o0] = scale(s0, edt) + scale(a.in1[i1] + N, R(0.5) * dt * eh);
       } else if (OP == OP_RK4_0) {
-        const Cx<R> s0 = a.in0[o];
-        a.out1[o] = scale(s0 + scale(N, R(0.5) * dt), eh);
-        a.out0[o] = scale(s0 + scale(N, dt / R(6)), edt);
+        const Cx<R> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0 + scale(N, R(0.5) * dt), eh);
+        a.out0[o0] = scale(s0 + scale(N, dt / R(6)), edt);
       } else if (OP == OP_RK4_1) {
-        const Cx<R> s0 = a.in0[o];
-        a.out1[o] = scale(s0, eh) + scale(N, R(0.5) * dt);
-        a.out0[o] = a.in1[o] + scale(N, dt / R(3) * eh);
+        const Cx<R> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0, eh) + scale(N, R(0.5) * dt);
+        a.out0[o0] = a.in1[i1] + scale(N, dt / R(3) * eh);
       } else if (OP == OP_RK4_2) {
-        const Cx<R> s0 = a.in0[o];
-        a.out1[o] = scale(s0, edt) + scale(N, dt * eh);
-        a.out0[o] = a.in1[o] + scale(N, dt / R(3) * eh);
+        const Cx<R> s0 = a.in0[i0];
+        a.out1[o1] = scale(s0, edt) + scale(N, dt * eh);
+        a.out0[o0] = a.in1[i1] + scale(N, dt / R(3) * eh);
       } else {  // OP_RK4_3
-        a.out0[o] = a.in1[o] + scale(N, dt / R(6));
+        a.out0[o0] = a.in1[i1] + scale(N, dt / R(6));
       }
     }
   }
 }
 
 // ------------------------------------------------------------------ tables
-// Phase factors exp(2 pi i k s / N) per axis, FP64 sincospi, rounded once:
-// ph[0..N) for k_x, ph[N..2N) for k_y, ph[2N..2N+N/2+1) for k_z.
-template <typename R>
-__global__ void k_phase(Cx<R>* ph, int n, int h, double sx, double sy, double sz) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * n + h) return;
-  int k;
-  double s;
-  if (t < n) { k = kval(t, n); s = sx; }
-  else if (t < 2 * n) { k = kval(t - n, n); s = sy; }
-  else { k = t - 2 * n; s = sz; }
-  double sn, cs;
-  sincospi(2.0 * (double)k * s / (double)n, &sn, &cs);
-  ph[t] = cx(R(cs), R(sn));
-}
-
 // Integrating factors exp(-nu k^2 tau) for tau = dt/2 and dt, FP64 exp, rounded once.
 template <typename R>
 __global__ void k_etab(R* eh, R* edt, long long k2top, double nu, double dt) {
