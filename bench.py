@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schemes", default="random,approx,exact,rk4")
     ap.add_argument("--copy-mb", type=int, default=0,
-                    help="first run 3 device-to-device copies of this many MiB (counter calibration)")
+                    help="first run 3 elementwise copies of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
@@ -181,10 +181,11 @@ def main():
         sys.exit(1)
     ns.lib()
     if args.copy_mb:
+        # counter calibration: an elementwise kernel that reads and writes copy_mb MiB once
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     K, W = args.steps, args.warmup

@@ -20,6 +20,18 @@ namespace ns {
 constexpr int kFastL = 16;
 constexpr int kFastLp = kFastL + 1;
 
+// Branch-free masked load: the address is clamped to element 0 when `ok` is
+// false and the value multiplied by 0 (the arrays hold finite values), so the
+// load is unconditional and a thread issues all of its loads back to back
+// before the first use (a select would let the compiler turn the load back into
+// a branch with a wait right behind it).
+template <typename T>
+__device__ __forceinline__ Cx<T> ld_masked(const Cx<T>* __restrict__ p, long long idx, bool ok) {
+  const Cx<T> v = p[ok ? idx : 0];
+  const T m = ok ? T(1) : T(0);
+  return cx(v.re * m, v.im * m);
+}
+
 // One line plan: N points over TPL threads, inverse and forward radix lists.
 template <int N_, int TPL_, typename Inv_, typename Fwd_>
 struct LinePlan {
@@ -76,28 +88,37 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   const int c1 = (f < 3) ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
   const int c2 = (f == 3) ? 1 : (f == 4 ? 2 : 0);
   const float kyf = float(ky), kzf = float(kz);
-  Cx<float> v[EPT];
+  Cx<float> v[EPT], a2[EPT];
+  bool ok[EPT];
+  long long idx[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::in_pos(t, i);
-    const int kx = kval(p, N);
-    Cx<float> val = cx(0.f, 0.f);
-    if (col && retained(g, kx, ky, kz)) {
-      const long long idx = (long long)p * N * ls.pitch + sbase;
-      const Cx<float> a1 = S[c1 * ls.cs + idx];
-      if (f < 3) {
-        val = a1;
-      } else {
-        const Cx<float> a2 = S[c2 * ls.cs + idx];
-        const float kxf = float(kx);
-        // omega_x = i(ky u_z - kz u_y), omega_y = i(kz u_x - kx u_z), omega_z = i(kx u_y - ky u_x)
-        const float w1 = (f == 3) ? kyf : (f == 4 ? kzf : kxf);
-        const float w2 = (f == 3) ? kzf : (f == 4 ? kxf : kyf);
-        val = mul_i(scale(a1, w1) - scale(a2, w2));
-      }
-      if (sh.on) val = cmul(val, cmul(phx[p], phyz));
+    ok[i] = col && retained(g, kval(p, N), ky, kz);
+    idx[i] = (long long)p * N * ls.pitch + sbase;
+  }
+  // straight-line load loops (one per case) so that all loads issue before the first wait
+  if (f < 3) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) v[i] = ld_masked(S + c1 * ls.cs, idx[i], ok[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      v[i] = ld_masked(S + c1 * ls.cs, idx[i], ok[i]);
+      a2[i] = ld_masked(S + c2 * ls.cs, idx[i], ok[i]);
     }
-    v[i] = val;
+    // omega_x = i(ky u_z - kz u_y), omega_y = i(kz u_x - kx u_z), omega_z = i(kx u_y - ky u_x)
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const float kxf = float(kval(F::in_pos(t, i), N));
+      const float w1 = (f == 3) ? kyf : (f == 4 ? kzf : kxf);
+      const float w2 = (f == 3) ? kzf : (f == 4 ? kxf : kyf);
+      v[i] = mul_i(scale(v[i], w1) - scale(a2[i], w2));
+    }
+  }
+  if (sh.on) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) v[i] = cmul(v[i], cmul(phx[F::in_pos(t, i)], phyz));
   }
   F::run(v, t, lv, tw);
   if (col) {
@@ -130,7 +151,7 @@ f_ypass(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, G
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::in_pos(t, i);
-    v[i] = (col && (S < 0 || abs(kval(p, N)) <= yb)) ? base[(long long)p * g.kzp] : cx(0.f, 0.f);
+    v[i] = ld_masked(base, (long long)p * g.kzp, col && (S < 0 || abs(kval(p, N)) <= yb));
   }
   F::run(v, t, lv, tw);
   if (col) {
@@ -168,21 +189,32 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   float fx[EPT], fy[EPT], fz[EPT];
   Cx<float> z[2][EPT];
   Cx<float> v[EPT];
+  // raw half-spectrum pairs of the slices, loaded two slices ahead so that the
+  // loads overlap the transforms (the barriers inside a transform keep the
+  // compiler from moving later loads above it)
+  Cx<float> ra[2][EPT], rb[2][EPT];
+  auto fetch = [&](int q, Cx<float>* a, Cx<float>* b) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int pos = FI::in_pos(t, i);
+      const int k = pos <= HN ? pos : N - pos;
+      a[i] = ld_masked(src + (2 * q) * g.wcomp, k, k < g.kzn);
+      b[i] = ld_masked(src + (2 * q + 1) * g.wcomp, k, k < g.kzn);
+    }
+  };
+  fetch(0, ra[0], rb[0]);
+  fetch(1, ra[1], rb[1]);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int pos = FI::in_pos(t, i);
-      const int k = pos <= HN ? pos : N - pos;
-      Cx<float> a = cx(0.f, 0.f), bb = cx(0.f, 0.f);
-      if (k < g.kzn) {
-        a = src[(2 * q) * g.wcomp + k];
-        bb = src[(2 * q + 1) * g.wcomp + k];
-      }
+      const Cx<float> a = ra[q & 1][i], bb = rb[q & 1][i];
       if (pos == 0 || pos == HN) v[i] = cx(a.re, bb.re);
       else if (pos < HN) v[i] = cx(a.re - bb.im, a.im + bb.re);
       else v[i] = cx(a.re + bb.im, bb.re - a.im);
     }
+    if (q == 0) fetch(2, ra[0], rb[0]);
     FI::run(v, t, lv, tw);
     if (q < 2) {
 #pragma unroll
@@ -251,11 +283,16 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
     if (sh.on) phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
     const bool col = kz < g.kzn;
     const Cx<float>* src = W + (long long)yi * g.kzp + kz;
+    // field f + 1 is loaded while field f is transformed
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) r[0][i] = ld_masked(src, (long long)F::in_pos(t, i) * N * g.kzp, col);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
+      if (f < 2) {
 #pragma unroll
-      for (int i = 0; i < EPT; ++i)
-        r[f][i] = col ? src[f * g.wcomp + (long long)F::in_pos(t, i) * N * g.kzp] : cx(0.f, 0.f);
+        for (int i = 0; i < EPT; ++i)
+          r[f + 1][i] = ld_masked(src + (f + 1) * g.wcomp, (long long)F::in_pos(t, i) * N * g.kzp, col);
+      }
       F::run(r[f], t, lv, tw);
     }
   }
@@ -263,8 +300,35 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
   Cx<float> phyz = cx(1.f, 0.f);
   if (sh.on && active && kz < g.kzn) phyz = cmul(phase1<float>(ky, sh.s[1], N), phase1<float>(kz, sh.s[2], N));
+  // stage operands, loaded for a chunk of points before that chunk's stores (out0
+  // may alias an operand, which keeps the compiler from hoisting loads above
+  // stores): all points for one-operand stages, half of them for two-operand ones
+  constexpr bool need0 = (OP == OP_HEUN1 || OP == OP_EX1B || OP == OP_EX2B || OP == OP_RK4_0 ||
+                          OP == OP_RK4_1 || OP == OP_RK4_2);
+  constexpr bool need1 = (OP == OP_AVG || OP == OP_HEUN2 || OP == OP_EX1B || OP == OP_EX2B ||
+                          OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3);
+  constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
+  for (int c0 = 0; c0 < EPT; c0 += CH) {
+  Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const int p = F::out_pos(t, c0 + j);
+    const bool ok = active && kz < g.kzn && retained(g, kval(p, N), ky, kz);
+    if constexpr (need0) {
+      const long long ii0 = lay_at(a.li0, p, yi, kz, N);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s0v[c][j] = ld_masked(a.in0 + c * a.li0.cs, ii0, ok);
+    }
+    if constexpr (need1) {
+      const long long ii1 = lay_at(a.li1, p, yi, kz, N);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s1v[c][j] = ld_masked(a.in1 + c * a.li1.cs, ii1, ok);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const int i = c0 + j;
     const int p = F::out_pos(t, i);
     const int kx = kval(p, N);
     const long long io0 = lay_at(a.lo0, p, yi, kz, N);
@@ -277,7 +341,6 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       continue;
     }
     const long long io1 = lay_at(a.lo1, p, yi, kz, N);
-    const long long ii0 = lay_at(a.li0, p, yi, kz, N), ii1 = lay_at(a.li1, p, yi, kz, N);
     Cx<float> Fv[3] = {scale(r[0][i], inv_n3), scale(r[1][i], inv_n3), scale(r[2][i], inv_n3)};
     if (sh.on) {
       const Cx<float> phi = cmul(phx[p], phyz);
@@ -302,40 +365,39 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long o0 = c * a.lo0.cs + io0, o1 = c * a.lo1.cs + io1;
-      const long long i0 = c * a.li0.cs + ii0, i1 = c * a.li1.cs + ii1;
       const Cx<float> Nv = Fv[c];
+      Cx<float> s0 = cx(0.f, 0.f), s1 = cx(0.f, 0.f);
+      if constexpr (need0) s0 = s0v[c][j];
+      if constexpr (need1) s1 = s1v[c][j];
       if (OP == OP_STORE) {
         a.out0[o0] = Nv;
       } else if (OP == OP_AVG) {
-        a.out0[o0] = scale(a.in1[i1] + Nv, 0.5f);
+        a.out0[o0] = scale(s1 + Nv, 0.5f);
       } else if (OP == OP_HEUN1) {
         Cx<float> O = cx(0.f, 0.f);
         if (a.force != nullptr && k2 >= 4 && k2 <= 9) O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
-        const Cx<float> s0 = a.in0[i0];
         a.out1[o1] = scale(s0 + scale(Nv + O, dt), edt);
         a.out0[o0] = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
       } else if (OP == OP_HEUN2) {
-        a.out0[o0] = a.in1[i1] + scale(Nv, 0.5f * dt * eh);
+        a.out0[o0] = s1 + scale(Nv, 0.5f * dt * eh);
       } else if (OP == OP_EX1B) {
-        a.out0[o0] = scale(a.in0[i0] + scale(a.in1[i1] + Nv, 0.25f * dt), eh);
+        a.out0[o0] = scale(s0 + scale(s1 + Nv, 0.25f * dt), eh);
       } else if (OP == OP_EX2B) {
-        a.out0[o0] = scale(a.in0[i0], edt) + scale(a.in1[i1] + Nv, 0.5f * dt * eh);
+        a.out0[o0] = scale(s0, edt) + scale(s1 + Nv, 0.5f * dt * eh);
       } else if (OP == OP_RK4_0) {
-        const Cx<float> s0 = a.in0[i0];
         a.out1[o1] = scale(s0 + scale(Nv, 0.5f * dt), eh);
         a.out0[o0] = scale(s0 + scale(Nv, dt / 6.f), edt);
       } else if (OP == OP_RK4_1) {
-        const Cx<float> s0 = a.in0[i0];
         a.out1[o1] = scale(s0, eh) + scale(Nv, 0.5f * dt);
-        a.out0[o0] = a.in1[i1] + scale(Nv, dt / 3.f * eh);
+        a.out0[o0] = s1 + scale(Nv, dt / 3.f * eh);
       } else if (OP == OP_RK4_2) {
-        const Cx<float> s0 = a.in0[i0];
         a.out1[o1] = scale(s0, edt) + scale(Nv, dt * eh);
-        a.out0[o0] = a.in1[i1] + scale(Nv, dt / 3.f * eh);
+        a.out0[o0] = s1 + scale(Nv, dt / 3.f * eh);
       } else {
-        a.out0[o0] = a.in1[i1] + scale(Nv, dt / 6.f);
+        a.out0[o0] = s1 + scale(Nv, dt / 6.f);
       }
     }
+  }
   }
 }
 
