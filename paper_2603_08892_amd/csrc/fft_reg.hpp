@@ -64,6 +64,23 @@ constexpr long double ct_sin2pi(long long num, long long den) {
   return ct_cos2pi(4 * num - den, 4 * den);  // sin x = cos(x - pi/2)
 }
 
+// cos and sin of 2 pi t / R for t < R, tabulated at compile time (a constexpr
+// variable is evaluated by the compiler; indexed with unrolled loop counters the
+// entries fold into immediates)
+template <int R>
+struct CtTable {
+  double c[R], s[R];
+};
+template <int R>
+constexpr CtTable<R> make_ct_table() {
+  CtTable<R> tab{};
+  for (int t = 0; t < R; ++t) {
+    tab.c[t] = (double)ct_cos2pi(t, R);
+    tab.s[t] = (double)ct_sin2pi(t, R);
+  }
+  return tab;
+}
+
 // ---------------------------------------------------------------- register DFTs
 template <int R, int S, typename T>
 __device__ __forceinline__ void rdft(Cx<T>* a);
@@ -72,6 +89,7 @@ __device__ __forceinline__ void rdft(Cx<T>* a);
 template <int A, int B, int S, typename T>
 __device__ __forceinline__ void rdft_split(Cx<T>* a) {
   constexpr int R = A * B;
+  constexpr CtTable<R> tab = make_ct_table<R>();
   Cx<T> y[A][B];
 #pragma unroll
   for (int n2 = 0; n2 < B; ++n2) {
@@ -84,8 +102,8 @@ __device__ __forceinline__ void rdft_split(Cx<T>* a) {
       if (n2 * k1 == 0) {
         y[k1][n2] = col[k1];
       } else {
-        const T c = T(ct_cos2pi((long long)n2 * k1, R));
-        const T s = T(S * ct_sin2pi((long long)n2 * k1, R));
+        const T c = T(tab.c[(n2 * k1) % R]);
+        const T s = T(S * tab.s[(n2 * k1) % R]);
         y[k1][n2] = cx(col[k1].re * c - col[k1].im * s, col[k1].re * s + col[k1].im * c);
       }
     }

@@ -403,14 +403,12 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
 
 // Specialised sizes (FP32).  The forward radix list is the inverse one reversed.
 using LP64 = LinePlan<64, 8, Radices<8, 8>, Radices<8, 8>>;
-using LP128a = LinePlan<128, 8, Radices<8, 16>, Radices<16, 8>>;
 using LP128b = LinePlan<128, 16, Radices<8, 4, 4>, Radices<4, 4, 8>>;
 using LP192 = LinePlan<192, 16, Radices<12, 4, 4>, Radices<4, 4, 12>>;
-using LP256a = LinePlan<256, 16, Radices<16, 16>, Radices<16, 16>>;
 using LP256b = LinePlan<256, 32, Radices<8, 8, 4>, Radices<4, 8, 8>>;
 using Fast64 = FastCfg<LP64, LP64, LP64, 16, LP64>;
-using Fast128 = FastCfg<LP128a, LP128a, LP128b, 16, LP128b>;
+using Fast128 = FastCfg<LP128b, LP128b, LP128b, 8, LP128b>;
 using Fast192 = FastCfg<LP192, LP192, LP192, 8, LP192>;
-using Fast256 = FastCfg<LP256a, LP256a, LP256b, 8, LP256b>;
+using Fast256 = FastCfg<LP256b, LP256b, LP256b, 8, LP256b>;
 
 }  // namespace ns

@@ -24,6 +24,12 @@ def test_header_and_binding_agree():
     assert sorted(ns.ABI_FUNCTIONS) == _declared()
 
 
+def test_pass_names_match_header():
+    with open(os.path.join(ROOT, "include", "ns.h")) as f:
+        m = re.search(r"#define NS_NUM_PASSES (\d+)", f.read())
+    assert int(m.group(1)) == len(ns.PASS_NAMES)
+
+
 def test_library_exports_every_declared_symbol():
     L = ns.lib()
     for name in _declared():
