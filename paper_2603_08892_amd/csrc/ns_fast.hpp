@@ -20,16 +20,38 @@ namespace ns {
 constexpr int kFastL = 16;
 constexpr int kFastLp = kFastL + 1;
 
-// Branch-free masked load: the address is clamped to element 0 when `ok` is
-// false and the value multiplied by 0 (the arrays hold finite values), so the
-// load is unconditional and a thread issues all of its loads back to back
-// before the first use (a select would let the compiler turn the load back into
-// a branch with a wait right behind it).
-template <typename T>
-__device__ __forceinline__ Cx<T> ld_masked(const Cx<T>* __restrict__ p, long long idx, bool ok) {
-  const Cx<T> v = p[ok ? idx : 0];
-  const T m = ok ? T(1) : T(0);
+// Addressing: a block-uniform base pointer (a state component or scratch field)
+// plus a per-lane 32-bit element offset.  Every specialised size keeps a
+// component below 2^24 elements, so the byte offset fits 32 bits, the base stays
+// in scalar registers and the index arithmetic is 32-bit.
+__device__ __forceinline__ Cx<float> ld_off(const Cx<float>* __restrict__ base, uint32_t off) {
+  return *reinterpret_cast<const Cx<float>*>(reinterpret_cast<const char*>(base) + off * 8u);
+}
+__device__ __forceinline__ void st_off(Cx<float>* __restrict__ base, uint32_t off, Cx<float> v) {
+  *reinterpret_cast<Cx<float>*>(reinterpret_cast<char*>(base) + off * 8u) = v;
+}
+
+// Branch-free masked load: the offset is clamped to element 0 of the (valid)
+// base when `ok` is false and the value multiplied by 0 (the arrays hold finite
+// values), so the load is unconditional and a thread issues all of its loads back
+// to back before the first use (a select would let the compiler turn the load
+// back into a branch with a wait right behind it).
+__device__ __forceinline__ Cx<float> ld_masked(const Cx<float>* __restrict__ base, uint32_t off, bool ok) {
+  const Cx<float> v = ld_off(base, ok ? off : 0u);
+  const float m = ok ? 1.f : 0.f;
   return cx(v.re * m, v.im * m);
+}
+
+// Truncation test in 32-bit arithmetic (|k_i| <= N/2 <= 128 here).
+__device__ __forceinline__ bool retained32(const Geom& g, int kx, int ky, int kz) {
+  if (g.mask == 0) return kx * kx + ky * ky + kz * kz <= (int)g.k2max;
+  return abs(kx) <= g.kmax && abs(ky) <= g.kmax && kz <= g.kmax;
+}
+
+// Shift factors of the block's 16 k_z columns on row k_y (FP64, rounded once per
+// axis like phase1), computed by 16 threads into LDS.
+__device__ __forceinline__ void phase_cols(Cx<float>* phc, int ky, int kz0, const Shift& sh, int n, int tid) {
+  if (tid < kFastL) phc[tid] = cmul(phase1<float>(ky, sh.s[1], n), phase1<float>(kz0 + tid, sh.s[2], n));
 }
 
 // One line plan: N points over TPL threads, inverse and forward radix lists.
@@ -66,46 +88,51 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   using F = RegFft<N, TPL, +1, typename C::Inv>;
   __shared__ Cx<float> tw[N];
   __shared__ Cx<float> phx[N];
+  __shared__ Cx<float> phc[kFastL];
   __shared__ Cx<float> xb[N * kFastLp];
   const int tid = threadIdx.x;
   const int l = tid % kFastL, t = tid / kFastL;
   const int b = blockIdx.x;
   const int f = (b >> 3) % 6;
   const int2 tile = tiles[8 * (b / 48) + (b & 7)];
-  const int yi = tile.x, kz = tile.y + l;
+  const int yi = tile.x, kz0 = tile.y, kz = kz0 + l;
   const int ky = kval(yi, N);
   for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
   const bool col = kz < g.kzn;
   Cx<float> phyz = cx(1.f, 0.f);
   if (sh.on) {
     phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
-    if (col) phyz = cmul(phase1<float>(ky, sh.s[1], N), phase1<float>(kz, sh.s[2], N));
+    phase_cols(phc, ky, kz0, sh, N, tid);
     __syncthreads();
+    phyz = phc[l];
   }
   const LineView<float, kFastLp> lv{xb + l};
-  const long long sbase = (long long)yi * ls.pitch + kz;
+  // element (k_x index p, yi, kz) of a component: offset p N pitch + yi pitch + kz
+  const uint32_t sbase = (uint32_t)(yi * ls.pitch + kz0) + l, sstep = (uint32_t)(N * ls.pitch);
   // field f = sum_c coef_c(k) u_c: u_x, u_y, u_z, then omega = i k x u
   const int c1 = (f < 3) ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
   const int c2 = (f == 3) ? 1 : (f == 4 ? 2 : 0);
+  const Cx<float>* S1 = S + c1 * ls.cs;
+  const Cx<float>* S2 = S + c2 * ls.cs;
   const float kyf = float(ky), kzf = float(kz);
   Cx<float> v[EPT], a2[EPT];
   bool ok[EPT];
-  long long idx[EPT];
+  uint32_t idx[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::in_pos(t, i);
-    ok[i] = col && retained(g, kval(p, N), ky, kz);
-    idx[i] = (long long)p * N * ls.pitch + sbase;
+    ok[i] = col && retained32(g, kval(p, N), ky, kz);
+    idx[i] = (uint32_t)p * sstep + sbase;
   }
   // straight-line load loops (one per case) so that all loads issue before the first wait
   if (f < 3) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) v[i] = ld_masked(S + c1 * ls.cs, idx[i], ok[i]);
+    for (int i = 0; i < EPT; ++i) v[i] = ld_masked(S1, idx[i], ok[i]);
   } else {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      v[i] = ld_masked(S + c1 * ls.cs, idx[i], ok[i]);
-      a2[i] = ld_masked(S + c2 * ls.cs, idx[i], ok[i]);
+      v[i] = ld_masked(S1, idx[i], ok[i]);
+      a2[i] = ld_masked(S2, idx[i], ok[i]);
     }
     // omega_x = i(ky u_z - kz u_y), omega_y = i(kz u_x - kx u_z), omega_z = i(kx u_y - ky u_x)
 #pragma unroll
@@ -122,9 +149,10 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   }
   F::run(v, t, lv, tw);
   if (col) {
-    Cx<float>* out = W + f * g.wcomp + (long long)yi * g.kzp + kz;
+    Cx<float>* out = W + f * g.wcomp;
+    const uint32_t obase = (uint32_t)(yi * g.kzp + kz0) + l, ostep = (uint32_t)(N * g.kzp);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) out[(long long)F::out_pos(t, i) * N * g.kzp] = v[i];
+    for (int i = 0; i < EPT; ++i) st_off(out, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
   }
 }
 
@@ -145,20 +173,21 @@ f_ypass(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, G
   const int yb = ybound(g, kz0);
   for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
   const bool col = kz < g.kzn;
-  Cx<float>* base = W + f * g.wcomp + (long long)x * N * g.kzp + kz;
+  Cx<float>* base = W + f * g.wcomp;
+  const uint32_t rbase = (uint32_t)(x * N * g.kzp + kz0) + l;
   const LineView<float, kFastLp> lv{xb + l};
   Cx<float> v[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::in_pos(t, i);
-    v[i] = ld_masked(base, (long long)p * g.kzp, col && (S < 0 || abs(kval(p, N)) <= yb));
+    v[i] = ld_masked(base, (uint32_t)(p * g.kzp) + rbase, col && (S < 0 || abs(kval(p, N)) <= yb));
   }
   F::run(v, t, lv, tw);
   if (col) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int p = F::out_pos(t, i);
-      if (S > 0 || abs(kval(p, N)) <= yb) base[(long long)p * g.kzp] = v[i];
+      if (S > 0 || abs(kval(p, N)) <= yb) st_off(base, (uint32_t)(p * g.kzp) + rbase, v[i]);
     }
   }
 }
@@ -182,10 +211,10 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   __shared__ Cx<float> sp[P * N];   // spectrum of f_x + i f_y
   const int tid = threadIdx.x;
   const int p = tid / TPL, t = tid % TPL;
-  const long long line = (long long)blockIdx.x * P + p;
+  const uint32_t line0 = (uint32_t)blockIdx.x * P;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   const LineView<float, 1> lv{xb + p * LP};
-  const Cx<float>* src = W + line * g.kzp;
+  const uint32_t lbase = (line0 + p) * (uint32_t)g.kzp;
   float fx[EPT], fy[EPT], fz[EPT];
   Cx<float> z[2][EPT];
   Cx<float> v[EPT];
@@ -198,8 +227,8 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
     for (int i = 0; i < EPT; ++i) {
       const int pos = FI::in_pos(t, i);
       const int k = pos <= HN ? pos : N - pos;
-      a[i] = ld_masked(src + (2 * q) * g.wcomp, k, k < g.kzn);
-      b[i] = ld_masked(src + (2 * q + 1) * g.wcomp, k, k < g.kzn);
+      a[i] = ld_masked(W + (2 * q) * g.wcomp, lbase + k, k < g.kzn);
+      b[i] = ld_masked(W + (2 * q + 1) * g.wcomp, lbase + k, k < g.kzn);
     }
   };
   fetch(0, ra[0], rb[0]);
@@ -241,14 +270,13 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
 #pragma unroll
   for (int i = 0; i < EPT; ++i) xb[p * LP + FF::out_pos(t, i)] = v[i];
   __syncthreads();
-  const long long line0 = (long long)blockIdx.x * P;
   for (int idx = tid; idx < P * g.kzn; idx += NT) {
     const int k = idx % g.kzn, pp = idx / g.kzn;
     const Cx<float> c1 = sp[pp * N + k], c2 = sp[pp * N + ((N - k) % N)];
-    const long long off = (line0 + pp) * g.kzp + k;
-    W[off] = cx(0.5f * (c1.re + c2.re), 0.5f * (c1.im - c2.im));
-    W[g.wcomp + off] = cx(0.5f * (c1.im + c2.im), -0.5f * (c1.re - c2.re));
-    W[2 * g.wcomp + off] = xb[pp * LP + k];
+    const uint32_t off = (line0 + pp) * (uint32_t)g.kzp + k;
+    st_off(W, off, cx(0.5f * (c1.re + c2.re), 0.5f * (c1.im - c2.im)));
+    st_off(W + g.wcomp, off, cx(0.5f * (c1.im + c2.im), -0.5f * (c1.re - c2.re)));
+    st_off(W + 2 * g.wcomp, off, xb[pp * LP + k]);
   }
 }
 
@@ -261,6 +289,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   using F = RegFft<N, TPL, -1, typename C::Fwd>;
   __shared__ Cx<float> tw[N];
   __shared__ Cx<float> phx[N];
+  __shared__ Cx<float> phc[kFastL];
   __shared__ Cx<float> xb[N * kFastLp];
   const int tid = threadIdx.x;
   const int l = tid % kFastL, t = tid / kFastL;
@@ -278,28 +307,31 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   const bool active = line_active(g, ky, kz0);
   const LineView<float, kFastLp> lv{xb + l};
   Cx<float> r[3][EPT];
+  Cx<float> phyz = cx(1.f, 0.f);
   if (active) {
     for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
-    if (sh.on) phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
+    if (sh.on) {
+      phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
+      phase_cols(phc, ky, kz0, sh, N, tid);
+    }
     const bool col = kz < g.kzn;
-    const Cx<float>* src = W + (long long)yi * g.kzp + kz;
+    const uint32_t wbase = (uint32_t)(yi * g.kzp + kz0) + l, wstep = (uint32_t)(N * g.kzp);
     // field f + 1 is loaded while field f is transformed
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) r[0][i] = ld_masked(src, (long long)F::in_pos(t, i) * N * g.kzp, col);
+    for (int i = 0; i < EPT; ++i) r[0][i] = ld_masked(W, (uint32_t)F::in_pos(t, i) * wstep + wbase, col);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       if (f < 2) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
-          r[f + 1][i] = ld_masked(src + (f + 1) * g.wcomp, (long long)F::in_pos(t, i) * N * g.kzp, col);
+          r[f + 1][i] = ld_masked(W + (f + 1) * g.wcomp, (uint32_t)F::in_pos(t, i) * wstep + wbase, col);
       }
-      F::run(r[f], t, lv, tw);
+      F::run(r[f], t, lv, tw);  // its barriers also publish phx and phc
     }
+    if (sh.on) phyz = phc[l];
   }
   if (kz >= g.h || (!a.full && kz >= g.kzn)) return;
   const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
-  Cx<float> phyz = cx(1.f, 0.f);
-  if (sh.on && active && kz < g.kzn) phyz = cmul(phase1<float>(ky, sh.s[1], N), phase1<float>(kz, sh.s[2], N));
   // stage operands, loaded for a chunk of points before that chunk's stores (out0
   // may alias an operand, which keeps the compiler from hoisting loads above
   // stores): all points for one-operand stages, half of them for two-operand ones
@@ -307,6 +339,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
                           OP == OP_RK4_1 || OP == OP_RK4_2);
   constexpr bool need1 = (OP == OP_AVG || OP == OP_HEUN2 || OP == OP_EX1B || OP == OP_EX2B ||
                           OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3);
+  constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
   constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
 #pragma unroll
   for (int c0 = 0; c0 < EPT; c0 += CH) {
@@ -314,14 +347,14 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int p = F::out_pos(t, c0 + j);
-    const bool ok = active && kz < g.kzn && retained(g, kval(p, N), ky, kz);
+    const bool ok = active && kz < g.kzn && retained32(g, kval(p, N), ky, kz);
     if constexpr (need0) {
-      const long long ii0 = lay_at(a.li0, p, yi, kz, N);
+      const uint32_t ii0 = (uint32_t)((p * N + yi) * a.li0.pitch + kz);
 #pragma unroll
       for (int c = 0; c < 3; ++c) s0v[c][j] = ld_masked(a.in0 + c * a.li0.cs, ii0, ok);
     }
     if constexpr (need1) {
-      const long long ii1 = lay_at(a.li1, p, yi, kz, N);
+      const uint32_t ii1 = (uint32_t)((p * N + yi) * a.li1.pitch + kz);
 #pragma unroll
       for (int c = 0; c < 3; ++c) s1v[c][j] = ld_masked(a.in1 + c * a.li1.cs, ii1, ok);
     }
@@ -331,16 +364,16 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
     const int i = c0 + j;
     const int p = F::out_pos(t, i);
     const int kx = kval(p, N);
-    const long long io0 = lay_at(a.lo0, p, yi, kz, N);
-    const bool ret = active && kz < g.kzn && retained(g, kx, ky, kz);
+    const uint32_t io0 = (uint32_t)((p * N + yi) * a.lo0.pitch + kz);
+    const bool ret = active && kz < g.kzn && retained32(g, kx, ky, kz);
     if (!ret) {
       // outside the retained set: zero in outputs that must be complete (full
       // mode, the caller's arrays); stage buffers are only read at retained modes
       if (a.full)
-        for (int c = 0; c < 3; ++c) a.out0[c * a.lo0.cs + io0] = cx(0.f, 0.f);
+        for (int c = 0; c < 3; ++c) st_off(a.out0 + c * a.lo0.cs, io0, cx(0.f, 0.f));
       continue;
     }
-    const long long io1 = lay_at(a.lo1, p, yi, kz, N);
+    const uint32_t io1 = use1 ? (uint32_t)((p * N + yi) * a.lo1.pitch + kz) : 0u;
     Cx<float> Fv[3] = {scale(r[0][i], inv_n3), scale(r[1][i], inv_n3), scale(r[2][i], inv_n3)};
     if (sh.on) {
       const Cx<float> phi = cmul(phx[p], phyz);
@@ -348,7 +381,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       Fv[1] = cmulc(Fv[1], phi);
       Fv[2] = cmulc(Fv[2], phi);
     }
-    const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
+    const int k2 = kx * kx + ky * ky + kz * kz;
     if (k2 == 0) {
       Fv[0] = Fv[1] = Fv[2] = cx(0.f, 0.f);
     } else {
@@ -364,37 +397,38 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
     const float dt = a.dt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const long long o0 = c * a.lo0.cs + io0, o1 = c * a.lo1.cs + io1;
+      Cx<float>* out0 = a.out0 + c * a.lo0.cs;
+      Cx<float>* out1 = use1 ? a.out1 + c * a.lo1.cs : nullptr;
       const Cx<float> Nv = Fv[c];
       Cx<float> s0 = cx(0.f, 0.f), s1 = cx(0.f, 0.f);
       if constexpr (need0) s0 = s0v[c][j];
       if constexpr (need1) s1 = s1v[c][j];
       if (OP == OP_STORE) {
-        a.out0[o0] = Nv;
+        st_off(out0, io0, Nv);
       } else if (OP == OP_AVG) {
-        a.out0[o0] = scale(s1 + Nv, 0.5f);
+        st_off(out0, io0, scale(s1 + Nv, 0.5f));
       } else if (OP == OP_HEUN1) {
         Cx<float> O = cx(0.f, 0.f);
         if (a.force != nullptr && k2 >= 4 && k2 <= 9) O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
-        a.out1[o1] = scale(s0 + scale(Nv + O, dt), edt);
-        a.out0[o0] = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
+        st_off(out1, io1, scale(s0 + scale(Nv + O, dt), edt));
+        st_off(out0, io0, scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh));
       } else if (OP == OP_HEUN2) {
-        a.out0[o0] = s1 + scale(Nv, 0.5f * dt * eh);
+        st_off(out0, io0, s1 + scale(Nv, 0.5f * dt * eh));
       } else if (OP == OP_EX1B) {
-        a.out0[o0] = scale(s0 + scale(s1 + Nv, 0.25f * dt), eh);
+        st_off(out0, io0, scale(s0 + scale(s1 + Nv, 0.25f * dt), eh));
       } else if (OP == OP_EX2B) {
-        a.out0[o0] = scale(s0, edt) + scale(s1 + Nv, 0.5f * dt * eh);
+        st_off(out0, io0, scale(s0, edt) + scale(s1 + Nv, 0.5f * dt * eh));
       } else if (OP == OP_RK4_0) {
-        a.out1[o1] = scale(s0 + scale(Nv, 0.5f * dt), eh);
-        a.out0[o0] = scale(s0 + scale(Nv, dt / 6.f), edt);
+        st_off(out1, io1, scale(s0 + scale(Nv, 0.5f * dt), eh));
+        st_off(out0, io0, scale(s0 + scale(Nv, dt / 6.f), edt));
       } else if (OP == OP_RK4_1) {
-        a.out1[o1] = scale(s0, eh) + scale(Nv, 0.5f * dt);
-        a.out0[o0] = s1 + scale(Nv, dt / 3.f * eh);
+        st_off(out1, io1, scale(s0, eh) + scale(Nv, 0.5f * dt));
+        st_off(out0, io0, s1 + scale(Nv, dt / 3.f * eh));
       } else if (OP == OP_RK4_2) {
-        a.out1[o1] = scale(s0, edt) + scale(Nv, dt * eh);
-        a.out0[o0] = s1 + scale(Nv, dt / 3.f * eh);
+        st_off(out1, io1, scale(s0, edt) + scale(Nv, dt * eh));
+        st_off(out0, io0, s1 + scale(Nv, dt / 3.f * eh));
       } else {
-        a.out0[o0] = s1 + scale(Nv, dt / 6.f);
+        st_off(out0, io0, s1 + scale(Nv, dt / 6.f));
       }
     }
   }
