@@ -1,0 +1,221 @@
+"""The measured workloads at their full sizes, in the launch configurations the
+benchmark times (the specialised FP32 passes at N = 128, 192, 256; the generic
+passes at N = 360 and 512), against the FP64 oracle or against properties that
+hold at any size.
+
+- Taylor-Green 128^3 (nu = 1/1600, dt = 2e-3): one step of each phase-shift
+  variant on the 128^3 grid and of RK4 on the 192^3 grid with 2/3 truncation
+  (matched k_max), and the FP64 spectra of the 128^3 state.
+- Forced isotropic turbulence 256^3: one random-shift step with the shell
+  forcing, nu from k_max eta = 1 at unit injection.
+- Adjoint 128^3: gradient of the final kinetic energy after 50 random-shift
+  steps (checkpoint every 10) against central differences on 20 seeded
+  directions.
+- 512^3 with 2/3 truncation and 360^3 with C_t = 0.9481 (the same k_max): the
+  Taylor-Green nonlinear term against its closed form, energy conservation,
+  zero divergence and mask support of the nonlinear term of a seeded isotropic
+  field, and the energy budget of one step.
+
+Tolerances: FP32 states 1e-5 relative L2 and 3e-4 relative to the largest entry
+per step (the stated FP32 field tolerance, as in test_gpu_parity); the
+increment S_new - E S0 is checked to 1e-2 relative L2, which is what the FP32
+rounding of a state about 1e3 times larger than its increment leaves; FP64
+spectra 1e-10 per bin.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import forcing as oforcing
+from oracle import grid, schemes, spectra
+from oracle import nonlinear as onl
+from paper_2603_08892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NU_TG, DT_TG = 1 / 1600, 2e-3
+
+
+def _solver(n, ct, nu, seed=2026, generic=False):
+    from paper_2603_08892_amd import ns
+    return ns.Solver(n, nu, ct, precision="fp32", seed=seed, generic=generic)
+
+
+def _f32(a):
+    return a.astype(np.complex64).astype(np.complex128)
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _check_state(got, want, what):
+    l2 = np.linalg.norm(got - want) / np.linalg.norm(want)
+    mx = np.abs(got - want).max() / np.abs(want).max()
+    assert l2 <= 1e-5 and mx <= 3e-4, f"{what}: rel L2 {l2:.3e} rel max {mx:.3e}"
+
+
+def _check_increment(got, want, lin, what):
+    d = np.linalg.norm((got - lin) - (want - lin)) / np.linalg.norm(want - lin)
+    assert d <= 1e-2, f"{what}: increment rel L2 {d:.3e}"
+
+
+@pytest.mark.parametrize("variant", ["random", "approx", "exact"])
+def test_taylor_green_128_phase_shift_step(variant):
+    n, ct = 128, 1.0
+    print(f"[workload] Taylor-Green {n}^3 PS-RK2 {variant}", flush=True)
+    s = _solver(n, ct, NU_TG)
+    model = onl.NSModel(n, NU_TG, grid.mask(n, ct))
+    u0 = inputs.taylor_green(n)
+    ud = s.to_device(u0)
+    if variant == "exact":
+        s.step_ps(ud, DT_TG, 1, "exact")
+        want = schemes.ps_exact(model, u0, DT_TG)
+    elif variant == "approx":
+        s.step_ps(ud, DT_TG, 1, "approx")
+        want = schemes.ps_heun(model, u0, DT_TG, (0, 0, 0))
+    else:
+        s.step_ps(ud, DT_TG, 1, "random", step0=3)
+        want = schemes.ps_heun(model, u0, DT_TG, oforcing.random_shift(2026, 3))
+    got = _host(ud)
+    _check_state(got, want, variant)
+    _check_increment(got, want, model.E(DT_TG) * u0, variant)
+
+
+def test_taylor_green_192_rk4_step():
+    n, ct = 192, 2 / 3
+    print(f"[workload] Taylor-Green {n}^3 RK4 C_t = 2/3", flush=True)
+    s = _solver(n, ct, NU_TG)
+    model = onl.NSModel(n, NU_TG, grid.mask(n, ct))
+    u0 = inputs.taylor_green(n)
+    ud = s.to_device(u0)
+    s.step_rk4(ud, DT_TG, 1)
+    want = schemes.rk4(model, u0, DT_TG)
+    got = _host(ud)
+    _check_state(got, want, "rk4")
+    _check_increment(got, want, model.E(DT_TG) * u0, "rk4")
+
+
+def test_matched_kmax_grids_retain_the_same_modes():
+    """PS-RK2 on 128^3 with C_t = 1 and RK4 on 192^3 with C_t = 2/3 keep the same set
+    of wavevectors k^2 <= 4095 (the pairing the speedups are quoted on)."""
+    from paper_2603_08892_amd import ns
+    assert ns.retained_bound(128, 1.0) == ns.retained_bound(192, 2 / 3) == 4095
+    assert grid.mask(128, 1.0).sum() == grid.mask(192, 2 / 3).sum()
+
+
+def test_taylor_green_128_spectra():
+    n, ct = 128, 1.0
+    print(f"[workload] Taylor-Green {n}^3 spectra", flush=True)
+    s = _solver(n, ct, NU_TG)
+    u = _f32(inputs.tg_perturbed(n, 4, grid.sphere_k2max(n, ct)))
+    ud = s.to_device(u)
+    nh = s.nonlinear(ud, ps_avg=True)
+    nh_h = _host(nh)
+    got = s.spectra(ud, nh)
+    want = spectra.spectra(u, NU_TG, nh_h)
+    for key in ("e_shell", "d_shell", "t_shell", "e_1d"):
+        g, w = got[key], want[key]
+        big = np.abs(w) > 1e-30 * np.abs(w).sum()
+        assert np.all(np.abs(g[big] - w[big]) <= 1e-10 * np.abs(w[big]) + 1e-14 * np.abs(w).max()), key
+    assert np.allclose(got["totals"][:3], want["totals"][:3], rtol=1e-10, atol=0)
+
+
+def test_forced_hit_256_step():
+    n, ct = 256, 1.0
+    nu = (ct * n / 2) ** (-4 / 3)        # k_max eta = 1 with eta = (nu^3 / eps)^(1/4), eps = 1
+    dt = 1e-3
+    print(f"[workload] forced HIT {n}^3 nu={nu:.3e}", flush=True)
+    s = _solver(n, ct, nu, seed=8)
+    model = onl.NSModel(n, nu, grid.mask(n, ct))
+    u0 = _f32(inputs.hit_initial(n, 21, grid.sphere_k2max(n, ct)))
+    ud = s.to_device(u0)
+    s.step_ps(ud, dt, 1, "random", forcing={"seed": 13, "injection": 1.0}, step0=7)
+    o = oforcing.forcing(u0, dt, 13, 7)
+    want = schemes.ps_heun(model, u0, dt, oforcing.random_shift(8, 7), forcing=o)
+    got = _host(ud)
+    _check_state(got, want, "forced HIT")
+    _check_increment(got, want, model.E(dt) * u0, "forced HIT")
+
+
+def test_adjoint_128_fifty_steps():
+    """Config: Taylor-Green plus a 1e-2 perturbation, 50 random-shift steps, checkpoint
+    every 10; the checkpointed autograd gradient of the final kinetic energy against
+    central differences of the GPU forward map along 20 seeded directions (FP32:
+    1e-3 relative, the digits FP32 differences of two energies keep)."""
+    import torch
+    from paper_2603_08892_amd.autograd import PSRK2Function, final_energy
+    n, ct, steps = 128, 1.0, 50
+    print(f"[workload] adjoint {n}^3, {steps} steps", flush=True)
+    s = _solver(n, ct, NU_TG, seed=5)
+    k2 = grid.sphere_k2max(n, ct)
+    u0 = s.to_device(_f32(inputs.tg_perturbed(n, 3, k2)))
+    al = inputs.random_shifts(11, steps)
+    x = u0.clone().requires_grad_(True)
+    J = final_energy(PSRK2Function.apply(x, s, DT_TG, steps, "random", al, 10))
+    J.backward()
+    g = x.grad.detach()
+
+    def run(y):
+        with torch.no_grad():
+            return final_energy(PSRK2Function.apply(y, s, DT_TG, steps, "random", al, 10)).item()
+
+    eps = 1e-3 * float(torch.linalg.vector_norm(u0))
+    gn = float(torch.linalg.vector_norm(g))
+    for seed in range(20):
+        v = s.to_device(inputs.random_solenoidal(n, 500 + seed, k2))
+        v = v / torch.linalg.vector_norm(v) + 0.5 * u0 / torch.linalg.vector_norm(u0)
+        fd = (run(u0 + eps * v) - run(u0 - eps * v)) / (2 * eps)
+        ad = float((g.conj() * v).real.sum())
+        assert abs(fd - ad) <= 1e-3 * max(abs(fd), 1e-3 * gn), (seed, fd, ad)
+
+
+@pytest.mark.parametrize("n,ct", [(512, 2 / 3), (360, 0.9481)])
+def test_large_grids_taylor_green_closed_form(n, ct):
+    """Generic passes (no specialised plan at these sizes); compared on the device."""
+    import torch
+    print(f"[workload] Taylor-Green closed form {n}^3 C_t={ct:.4f}", flush=True)
+    s = _solver(n, ct, NU_TG)
+    u = s.empty()
+    tg = inputs.taylor_green(8)          # the eight coefficients per component, placed at N
+    nz = np.argwhere(tg != 0)
+    for c, i, j, k in nz:
+        ii = i if i < 4 else n - (8 - i)
+        jj = j if j < 4 else n - (8 - j)
+        u[c, ii, jj, k] = complex(tg[c, i, j, k])
+    got = s.nonlinear(u)
+    want = torch.zeros_like(got)
+    for (kx, val) in [(2, 1j / 32), (-2, -1j / 32)]:
+        want[0, kx % n, 0, 2] = val
+        want[1, 0, kx % n, 2] = val
+    for kx in (2, -2):
+        want[2, kx % n, 0, 2] = -1j / 32
+        want[2, 0, kx % n, 2] = -1j / 32
+    err = float(torch.abs(got - want).max())
+    assert err <= 1e-5 / 32, err
+
+
+def test_large_grid_360_properties_and_energy_budget():
+    """Seeded isotropic field on 360^3 with C_t = 0.9481 (k_max of 512^3 at 2/3):
+    <u, N> = 0, k.N = 0, N = 0 outside the mask, and one random-shift step changes the
+    energy by the dissipation -2 nu sum w k^2 |u|^2 dt to O(dt^2)."""
+    n, ct, nu, dt = 360, 0.9481, 2e-3, 2e-5
+    print(f"[workload] {n}^3 C_t={ct} properties", flush=True)
+    s = _solver(n, ct, nu, seed=9)
+    k2max = grid.sphere_k2max(n, ct)
+    m = grid.mask(n, ct)
+    u = _f32(inputs.hit_initial(n, 33, k2max))
+    ud = s.to_device(u)
+    nh = _host(s.nonlinear(ud, shift=(0.3, 0.6, 0.15)))
+    scale = np.sqrt(spectra.inner(u, u) * spectra.inner(nh, nh))
+    assert abs(spectra.inner(u, nh)) <= 1e-5 * scale
+    kx, ky, kz = grid.kgrid(n)
+    div = kx * nh[0] + ky * nh[1] + kz * nh[2]
+    assert np.abs(div).max() <= 1e-5 * np.sqrt(k2max) * np.abs(nh).max()
+    assert np.all(nh[:, ~m] == 0)
+    # dE/dt = -nu sum w k^2 |u|^2 (<u, N> = 0); the step's O(dt^2) part is below 1e-2 at this dt
+    e0 = spectra.energy(u)
+    eps = nu * np.sum(grid.hermitian_weight(n) * grid.k2grid(n) * np.sum(np.abs(u) ** 2, axis=0))
+    s.step_ps(ud, dt, 1, "random", step0=2)
+    e1 = spectra.energy(_host(ud))
+    assert abs((e1 - e0) / dt + eps) <= 1e-2 * eps, ((e1 - e0) / dt, -eps)
