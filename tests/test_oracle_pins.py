@@ -159,6 +159,46 @@ def test_p3_double_aliases_survive_at_ct1_and_eight_shifts_clean():
     assert rel(onl.nonlinear_8(uh, m), clean) < 1e-13
 
 
+@pytest.mark.parametrize("n,ct", [(12, 1.0), (12, 0.97), (14, 1.0)])
+def test_p3_no_multiple_aliases_mask_leaves_no_double_alias(n, ct):
+    """"no_multiple_aliases" truncation (Fig. 7b): for inputs anywhere in the sphere,
+    every double- and triple-alias class (brute-force pair sums) is zero on the modes
+    the mask keeps; with the state inside the mask the isotropic pair average equals
+    the alias-free padded product.  The mask removes the continuous reach of the
+    double aliases, so on a small lattice it may remove modes no lattice pair reaches
+    (at N = 14 none is reached); at N = 12 most removed modes are reached."""
+    m = grid.mask(n, ct, "no_multiple_aliases")
+    sph = grid.mask(n, ct)
+    assert m.sum() < sph.sum() and np.all(sph[m])
+    cls = _alias_classes(inputs.random_solenoidal(n, 40 + n, grid.sphere_k2max(n, ct)), n)
+    for e, c in cls.items():
+        if sum(abs(v) for v in e) >= 2:
+            assert np.abs(c[:, m]).max() < 1e-13, e
+    reached = np.zeros_like(m)
+    for e, c in cls.items():
+        if sum(abs(v) for v in e) == 2:
+            reached |= np.abs(c).max(axis=0) > 1e-12
+    if n == 12:
+        assert reached[sph & ~m].mean() > 0.5
+    uh = inputs.random_solenoidal(n, 60 + n, grid.sphere_k2max(n, ct)) * m
+    assert rel(onl.nonlinear_ps(uh, m), onl.nonlinear_pad(uh, m)) < 1e-13
+
+
+def test_p3_no_multiple_aliases_equals_sphere_below_2sqrt2_over_3():
+    """Spherical truncation at C_t <= 2 sqrt(2)/3 already removes every double alias
+    (Patterson and Orszag, cited in Sec. "Extension to the multidimensional case"), so
+    the mask removes nothing there; at C_t = 1 it removes modes, and the pair average is
+    clean on what remains for a larger grid too."""
+    for n in (16, 24, 48):
+        for ct in (2 / 3, 0.9, 0.94, 2 * np.sqrt(2) / 3 - 1e-9):
+            assert np.array_equal(grid.mask(n, ct, "no_multiple_aliases"), grid.mask(n, ct)), (n, ct)
+        assert grid.mask(n, 1.0, "no_multiple_aliases").sum() < grid.mask(n, 1.0).sum()
+    n = 24
+    m = grid.mask(n, 1.0, "no_multiple_aliases")
+    uh = inputs.random_solenoidal(n, 77, grid.sphere_k2max(n, 1.0)) * m
+    assert rel(onl.nonlinear_ps(uh, m), onl.nonlinear_pad(uh, m)) < 1e-13
+
+
 # ----------------------------------------------------------------------------- P4, P5
 @pytest.mark.parametrize("ct,kind", [(1.0, "sphere"), (2 / 3, "sphere"), (0.9, "cube")])
 def test_p4_p5_energy_helicity_divergence(ct, kind):
