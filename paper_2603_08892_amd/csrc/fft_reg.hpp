@@ -152,10 +152,24 @@ __host__ __device__ constexpr int line_pitch(int n) { return n + n / 16 + 1; }
 // Stages of one transform on the registers v[b * R + m] (b < EPT/R) of thread t.
 // NS = points already combined.  Twiddles from the table tw[] (W_N^t, t < N).
 // Each exchange: barrier, write, barrier, read (the buffer may still be read by
-// the previous use, so the first barrier is kept).
+// the previous use, so the first barrier is kept).  WAVE: all TPL threads of a
+// line are in one wavefront, whose LDS operations complete in program order, so
+// the barriers only have to order the LDS accesses at wavefront scope (fences
+// around a wavefront barrier) instead of synchronising the whole block.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_barrier() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int N, int TPL, int S, int NS, int R, int... Rest>
 struct RegStages {
-  template <typename T, int ES>
+  template <bool WAVE, typename T, int ES>
   __device__ __forceinline__ static void run(Cx<T>* v, int t, const LineView<T, ES>& lv, const Cx<T>* tw) {
     constexpr int EPT = N / TPL;
     constexpr int NB = EPT / R;
@@ -176,7 +190,7 @@ struct RegStages {
     if constexpr (sizeof...(Rest) > 0) {
       constexpr int R2 = first_of<Rest...>();
       constexpr int NB2 = EPT / R2;
-      __syncthreads();
+      exchange_barrier<WAVE>();
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = t + TPL * b;
@@ -184,14 +198,14 @@ struct RegStages {
 #pragma unroll
         for (int m = 0; m < R; ++m) lv.at(q * NS * R + k + m * NS) = v[b * R + m];
       }
-      __syncthreads();
+      exchange_barrier<WAVE>();
 #pragma unroll
       for (int b = 0; b < NB2; ++b) {
         const int j = t + TPL * b;
 #pragma unroll
         for (int m = 0; m < R2; ++m) v[b * R2 + m] = lv.at(j + m * (N / R2));
       }
-      RegStages<N, TPL, S, NS * R, Rest...>::run(v, t, lv, tw);
+      RegStages<N, TPL, S, NS * R, Rest...>::template run<WAVE>(v, t, lv, tw);
     }
   }
   template <int F, int... X>
@@ -226,9 +240,10 @@ struct RegFft<N, TPL, S, Radices<Rs...>> {
   __device__ __forceinline__ static int in_pos(int t, int i) { return t + TPL * (i / R0) + (i % R0) * (N / R0); }
   // output position of register i (i = b * RL + m) of thread t after the last stage
   __device__ __forceinline__ static int out_pos(int t, int i) { return t + TPL * (i / RL) + (i % RL) * (N / RL); }
-  template <typename T, int ES>
+  template <bool WAVE = false, typename T, int ES>
   __device__ __forceinline__ static void run(Cx<T>* v, int t, const LineView<T, ES>& lv, const Cx<T>* tw) {
-    RegStages<N, TPL, S, 1, Rs...>::run(v, t, lv, tw);
+    static_assert(!WAVE || TPL <= 64, "a wavefront-local line fits in one wavefront");
+    RegStages<N, TPL, S, 1, Rs...>::template run<WAVE>(v, t, lv, tw);
   }
 };
 

@@ -42,10 +42,34 @@ __device__ __forceinline__ Cx<float> ld_masked(const Cx<float>* __restrict__ bas
   return cx(v.re * m, v.im * m);
 }
 
-// Truncation test in 32-bit arithmetic (|k_i| <= N/2 <= 128 here).
-__device__ __forceinline__ bool retained32(const Geom& g, int kx, int ky, int kz) {
-  if (g.mask == 0) return kx * kx + ky * ky + kz * kz <= (int)g.k2max;
-  return abs(kx) <= g.kmax && abs(ky) <= g.kmax && kz <= g.kmax;
+// Truncation test along one k_x line (fixed k_y, k_z) in 32-bit arithmetic
+// (|k_i| <= N/2 <= 128 here): every mask is k_x^2 <= hi2, and for the
+// no-multiple-aliases mask also lo2 < k_x^2 and (N - |k_x|)^2 > ah2, with
+// per-line thresholds.
+struct LineTest {
+  int hi2, lo2, ah2, n;
+  bool alias;  // the double-alias thresholds apply (block-uniform)
+  __device__ __forceinline__ bool operator()(int kx) const {
+    // evaluated without short-circuit branches, so masked loads stay unconditional
+    const int k2 = kx * kx, a = n - abs(kx);
+    return (k2 <= hi2) & (!alias | ((k2 > lo2) & (a * a > ah2)));
+  }
+};
+__device__ __forceinline__ LineTest line_test(const Geom& g, int ky, int kz) {
+  LineTest L{0, -1, -1, g.n, g.mask == 2};
+  if (g.mask == 1) {
+    L.hi2 = (abs(ky) <= g.kmax && kz <= g.kmax) ? g.kmax * g.kmax : -1;
+  } else {
+    const int k2 = (int)g.k2max;
+    L.hi2 = k2 - ky * ky - kz * kz;
+    if (g.mask == 2) {
+      // no double alias on (x, y), (x, z) or (y, z): see double_alias_free
+      const int b = g.n - abs(ky), c = g.n - abs(kz);
+      L.lo2 = 4 * k2 - b * b - c * c;
+      L.ah2 = max(4 * k2 - b * b - kz * kz, 4 * k2 - c * c - ky * ky);
+    }
+  }
+  return L;
 }
 
 // Shift factors of the block's 16 k_z columns on row k_y (FP64, rounded once per
@@ -118,10 +142,11 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   Cx<float> v[EPT], a2[EPT];
   bool ok[EPT];
   uint32_t idx[EPT];
+  const LineTest keep = line_test(g, ky, col ? kz : 0);  // (padding tiles carry a huge kz)
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::in_pos(t, i);
-    ok[i] = col && retained32(g, kval(p, N), ky, kz);
+    ok[i] = col && keep(kval(p, N));
     idx[i] = (uint32_t)p * sstep + sbase;
   }
   // straight-line load loops (one per case) so that all loads issue before the first wait
@@ -211,8 +236,10 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   __shared__ Cx<float> sp[P * N];   // spectrum of f_x + i f_y
   const int tid = threadIdx.x;
   const int p = tid / TPL, t = tid % TPL;
+  static_assert(64 % TPL == 0, "the threads of a line stay in one wavefront");
   const uint32_t line0 = (uint32_t)blockIdx.x * P;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  __syncthreads();  // the line transforms below synchronise only within a wavefront
   const LineView<float, 1> lv{xb + p * LP};
   const uint32_t lbase = (line0 + p) * (uint32_t)g.kzp;
   float fx[EPT], fy[EPT], fz[EPT];
@@ -244,7 +271,7 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
       else v[i] = cx(a.re + bb.im, bb.re - a.im);
     }
     if (q == 0) fetch(2, ra[0], rb[0]);
-    FI::run(v, t, lv, tw);
+    FI::template run<true>(v, t, lv, tw);
     if (q < 2) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i) z[q][i] = v[i];
@@ -260,12 +287,12 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) v[i] = cx(fx[i], fy[i]);
-  FF::run(v, t, lv, tw);
+  FF::template run<true>(v, t, lv, tw);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) sp[p * N + FF::out_pos(t, i)] = v[i];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) v[i] = cx(fz[i], 0.f);
-  FF::run(v, t, lv, tw);
+  FF::template run<true>(v, t, lv, tw);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) xb[p * LP + FF::out_pos(t, i)] = v[i];
@@ -341,13 +368,15 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
                           OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3);
   constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
   constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
+  const LineTest keep = line_test(g, ky, kz);
+  const bool line_kept = active && kz < g.kzn;
 #pragma unroll
   for (int c0 = 0; c0 < EPT; c0 += CH) {
   Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int p = F::out_pos(t, c0 + j);
-    const bool ok = active && kz < g.kzn && retained32(g, kval(p, N), ky, kz);
+    const bool ok = line_kept && keep(kval(p, N));
     if constexpr (need0) {
       const uint32_t ii0 = (uint32_t)((p * N + yi) * a.li0.pitch + kz);
 #pragma unroll
@@ -365,8 +394,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
     const int p = F::out_pos(t, i);
     const int kx = kval(p, N);
     const uint32_t io0 = (uint32_t)((p * N + yi) * a.lo0.pitch + kz);
-    const bool ret = active && kz < g.kzn && retained32(g, kx, ky, kz);
-    if (!ret) {
+    if (!(line_kept && keep(kx))) {
       // outside the retained set: zero in outputs that must be complete (full
       // mode, the caller's arrays); stage buffers are only read at retained modes
       if (a.full)

@@ -80,8 +80,11 @@ struct Layout {
 };
 
 bool retained_host(const Geom& g, long long kx, long long ky, long long kz) {
-  if (g.mask == 0) return kx * kx + ky * ky + kz * kz <= g.k2max;
-  return std::llabs(kx) <= g.kmax && std::llabs(ky) <= g.kmax && kz <= g.kmax;
+  if (g.mask == 1) return std::llabs(kx) <= g.kmax && std::llabs(ky) <= g.kmax && kz <= g.kmax;
+  if (kx * kx + ky * ky + kz * kz > g.k2max) return false;
+  if (g.mask == 0) return true;
+  const long long a = g.n - std::llabs(kx), b = g.n - std::llabs(ky), c = g.n - std::llabs(kz), k4 = 4 * g.k2max;
+  return a * a + b * b + kz * kz > k4 && a * a + c * c + ky * ky > k4 && b * b + c * c + kx * kx > k4;
 }
 
 int kval_host(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
@@ -95,7 +98,7 @@ int isqrt_host(long long v) {
 }
 
 int ybound_host(const Geom& g, int kz) {
-  if (g.mask == 0) return isqrt_host(g.k2max - (long long)kz * kz);
+  if (g.mask != 1) return isqrt_host(g.k2max - (long long)kz * kz);
   return kz <= g.kmax ? g.kmax : -1;
 }
 
@@ -110,12 +113,13 @@ const char* validate(const ns_config* c) {
   if (c == nullptr) return "config is NULL";
   if (!factor_ok(c->n, nullptr)) return "n must be 2^a 3^b 5^c with a >= 1 and 8 <= n <= 1024";
   if (c->precision != NS_FP32 && c->precision != NS_FP64) return "precision must be NS_FP32 or NS_FP64";
-  if (c->mask != NS_MASK_SPHERE && c->mask != NS_MASK_CUBE) return "mask must be NS_MASK_SPHERE or NS_MASK_CUBE";
+  if (c->mask != NS_MASK_SPHERE && c->mask != NS_MASK_CUBE && c->mask != NS_MASK_NO_MULTIPLE_ALIASES)
+    return "mask must be NS_MASK_SPHERE, NS_MASK_CUBE or NS_MASK_NO_MULTIPLE_ALIASES";
   if (c->flags & ~NS_CFG_GENERIC_PASSES) return "unknown config flags";
   if (!(c->nu >= 0.0) || !std::isfinite(c->nu)) return "nu must be finite and >= 0";
   if (!(c->ct > 0.0 && c->ct <= 1.0)) return "ct must satisfy 0 < ct <= 1";
   const double kmax = c->ct * c->n / 2.0;
-  if (c->mask == NS_MASK_SPHERE ? largest_int_below(kmax * kmax) < 1 : largest_int_below(kmax) < 1)
+  if (c->mask != NS_MASK_CUBE ? largest_int_below(kmax * kmax) < 1 : largest_int_below(kmax) < 1)
     return "ct too small: no non-zero mode is retained";
   return nullptr;
 }
@@ -129,7 +133,7 @@ bool make_layout(const ns_config* c, Layout* lay) {
   g.h = n / 2 + 1;
   g.mask = c->mask;
   const double kmax = c->ct * n / 2.0;
-  if (c->mask == NS_MASK_SPHERE) {
+  if (c->mask != NS_MASK_CUBE) {
     g.k2max = largest_int_below(kmax * kmax);
     g.kmax = isqrt_host(g.k2max);
     lay->k2top = g.k2max;
@@ -751,7 +755,7 @@ int64_t ns_retained_bound(const ns_config* cfg) {
   if (m) { g_last_error = m; return -1; }
   Layout lay;
   make_layout(cfg, &lay);
-  return cfg->mask == NS_MASK_SPHERE ? lay.g.k2max : lay.g.kmax;
+  return cfg->mask != NS_MASK_CUBE ? lay.g.k2max : lay.g.kmax;
 }
 
 ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx** out) {
@@ -851,7 +855,13 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
     if (forcing->k2_lo != 4 || forcing->k2_hi != 9) return fail(ctx, NS_ERR_ARG, "forcing shell must be 4 <= |k|^2 <= 9");
     if (!(forcing->injection > 0.0) || !std::isfinite(forcing->injection)) return fail(ctx, NS_ERR_ARG, "injection must be finite and > 0");
     const Geom& g = ctx->lay.g;
-    if (g.mask == 0 ? g.k2max < 9 : g.kmax < 3) return fail(ctx, NS_ERR_ARG, "forcing shell lies outside the retained set");
+    for (int kx = -3; kx <= 3; ++kx)
+      for (int ky = -3; ky <= 3; ++ky)
+        for (int kz = 0; kz <= 3; ++kz) {
+          const int k2 = kx * kx + ky * ky + kz * kz;
+          if (k2 >= 4 && k2 <= 9 && !retained_host(g, kx, ky, kz))
+            return fail(ctx, NS_ERR_ARG, "forcing shell lies outside the retained set");
+        }
   }
   if (alphas && variant == NS_PS_RANDOM)
     for (int i = 0; i < 3 * nsteps; ++i)

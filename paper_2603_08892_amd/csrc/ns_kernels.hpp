@@ -26,7 +26,7 @@ struct Geom {
   int kzp;          // k_z stride of the scratch fields (kzn rounded up)
   int L;            // k_z columns per strided tile (power of two)
   int lgL;          // log2(L)
-  int mask;         // 0 sphere, 1 cube
+  int mask;         // 0 sphere, 1 cube, 2 sphere without the double-alias reach
   int kmax;         // largest retained |k_i|
   long long k2max;  // sphere: largest retained |k|^2; cube: 3 kmax^2
   long long comp;   // state component stride, n*n*h
@@ -35,10 +35,19 @@ struct Geom {
 
 __device__ __forceinline__ int kval(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
+// No double alias reaches k from two inputs with |k|^2 <= K2max: for every pair of
+// axes the image of k nearest the origin, (N - |k_i|, N - |k_j|, k_l), is longer
+// than 2 sqrt(K2max).
+__device__ __forceinline__ bool double_alias_free(const Geom& g, int kx, int ky, int kz) {
+  const long long a = g.n - abs(kx), b = g.n - abs(ky), c = g.n - abs(kz), k4 = 4 * g.k2max;
+  return a * a + b * b + (long long)kz * kz > k4 && a * a + c * c + (long long)ky * ky > k4 &&
+         b * b + c * c + (long long)kx * kx > k4;
+}
+
 __device__ __forceinline__ bool retained(const Geom& g, int kx, int ky, int kz) {
-  if (g.mask == 0)
-    return (long long)kx * kx + (long long)ky * ky + (long long)kz * kz <= g.k2max;
-  return abs(kx) <= g.kmax && abs(ky) <= g.kmax && kz <= g.kmax;
+  if (g.mask == 1) return abs(kx) <= g.kmax && abs(ky) <= g.kmax && kz <= g.kmax;
+  if ((long long)kx * kx + (long long)ky * ky + (long long)kz * kz > g.k2max) return false;
+  return g.mask == 0 || double_alias_free(g, kx, ky, kz);
 }
 
 __device__ __forceinline__ int isqrt_ll(long long v) {
@@ -49,9 +58,10 @@ __device__ __forceinline__ int isqrt_ll(long long v) {
   return r;
 }
 
-// Largest |k_y| that can be retained on k_z plane kz (-1: none).
+// Largest |k_y| that can be retained on k_z plane kz (-1: none); for the
+// no-multiple-aliases mask the sphere's bound (a superset).
 __device__ __forceinline__ int ybound(const Geom& g, int kz) {
-  if (g.mask == 0) return isqrt_ll(g.k2max - (long long)kz * kz);
+  if (g.mask != 1) return isqrt_ll(g.k2max - (long long)kz * kz);
   return kz <= g.kmax ? g.kmax : -1;
 }
 

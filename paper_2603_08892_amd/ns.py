@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(PKG, "libns.so")
 
 NS_OK, NS_ERR_ARG, NS_ERR_SIZE, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(6)
 NS_FP32, NS_FP64 = 0, 1
-NS_MASK_SPHERE, NS_MASK_CUBE = 0, 1
+NS_MASK_SPHERE, NS_MASK_CUBE, NS_MASK_NO_MULTIPLE_ALIASES = 0, 1, 2
+MASKS = {"sphere": NS_MASK_SPHERE, "cube": NS_MASK_CUBE, "no_multiple_aliases": NS_MASK_NO_MULTIPLE_ALIASES}
 NS_PS_EXACT, NS_PS_APPROX, NS_PS_RANDOM = 0, 1, 2
 NS_NL_PS_AVG = 1
 VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM}
@@ -95,7 +96,7 @@ NS_CFG_GENERIC_PASSES = 1
 
 def make_config(n, nu, ct, mask="sphere", precision="fp32", seed=0, stream=None, generic=False):
     return NSConfig(int(n), NS_FP32 if precision == "fp32" else NS_FP64,
-                    NS_MASK_SPHERE if mask == "sphere" else NS_MASK_CUBE,
+                    MASKS[mask],
                     NS_CFG_GENERIC_PASSES if generic else 0, float(nu), float(ct), int(seed), stream)
 
 

@@ -43,6 +43,20 @@ def test_retained_bounds_match_oracle(n, ct):
     assert ns.retained_bound(n, ct, "cube") == grid.cube_kmax(n, ct)
 
 
+@pytest.mark.parametrize("n", [8, 12, 16, 32, 128, 192, 360])
+@pytest.mark.parametrize("ct", [2 / 3, 0.97, 1.0])
+def test_no_multiple_aliases_bound_is_the_sphere(n, ct):
+    assert ns.retained_bound(n, ct, "no_multiple_aliases") == grid.sphere_k2max(n, ct)
+
+
+def test_unknown_mask_rejected():
+    L = ns.lib()
+    cfg = ns.make_config(32, 0.1, 1.0)
+    cfg.mask = 3
+    assert L.ns_workspace_bytes(ctypes.byref(cfg)) == 0
+    assert b"mask" in L.ns_last_error(None)
+
+
 @pytest.mark.parametrize("n", [8, 16, 32, 128, 192, 360, 512, 1024])
 def test_num_shells_matches_oracle(n):
     assert ns.num_shells(n) == grid.n_shells(n)

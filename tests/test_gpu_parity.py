@@ -47,7 +47,7 @@ def _check(got, want, prec, what=""):
 
 
 def _field(n, ct, mask, seed, energy=None):
-    k2 = grid.sphere_k2max(n, ct) if mask == "sphere" else 3 * grid.cube_kmax(n, ct) ** 2
+    k2 = 3 * grid.cube_kmax(n, ct) ** 2 if mask == "cube" else grid.sphere_k2max(n, ct)
     u = inputs.random_solenoidal(n, seed, k2, energy=energy)
     return u * grid.mask(n, ct, mask)
 
@@ -58,6 +58,8 @@ NL_CASES = [
     (48, 1.0, "sphere", "fp32"), (32, 1.0, "sphere", "fp32"), (60, 2 / 3, "cube", "fp32"),
     (64, 1.0, "sphere", "fp32"), (96, 2 / 3, "sphere", "fp32"), (128, 1.0, "sphere", "fp32"),
     (128, 2 / 3, "cube", "fp32"), (192, 2 / 3, "sphere", "fp32"), (256, 1.0, "sphere", "fp32"),
+    (16, 1.0, "no_multiple_aliases", "fp64"), (24, 0.97, "no_multiple_aliases", "fp64"),
+    (64, 1.0, "no_multiple_aliases", "fp32"), (128, 1.0, "no_multiple_aliases", "fp32"),
 ]
 
 
@@ -85,6 +87,38 @@ def test_nonlinear_ignores_modes_outside_mask():
     got = _host(s.nonlinear(s.to_device(u)))
     _check(got, onl.nonlinear(u, m), "fp64")
     assert np.all(got[:, ~m] == 0)
+
+
+@pytest.mark.parametrize("n,ct", [(24, 1.0), (30, 0.98)])
+def test_no_multiple_aliases_pair_average_is_clean(n, ct):
+    """With the "no_multiple_aliases" truncation the GPU's isotropic pair average is the
+    alias-free (padded) product of the oracle, and the output is zero outside the mask
+    even for an input that fills every mode."""
+    s = _solver(n, ct, "no_multiple_aliases", "fp64")
+    m = grid.mask(n, ct, "no_multiple_aliases")
+    u = _field(n, ct, "no_multiple_aliases", 300 + n)
+    _check(_host(s.nonlinear(s.to_device(u), ps_avg=True)), onl.nonlinear_pad(u, m), "fp64", "clean")
+    full = inputs.random_solenoidal(n, 9, 3 * (n // 2) ** 2)
+    got = _host(s.nonlinear(s.to_device(full)))
+    _check(got, onl.nonlinear(full, m), "fp64", "full input")
+    assert np.all(got[:, ~m] == 0)
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "exact", "random"])
+def test_no_multiple_aliases_step(scheme):
+    n, ct, nu, dt = 32, 1.0, 0.02, 0.01
+    s = _solver(n, ct, "no_multiple_aliases", "fp64", nu=nu, seed=12)
+    m = grid.mask(n, ct, "no_multiple_aliases")
+    model = onl.NSModel(n, nu, m)
+    u = _field(n, ct, "no_multiple_aliases", 41, energy=0.5)
+    ud = s.to_device(u)
+    if scheme == "rk4":
+        s.step_rk4(ud, dt, 1)
+    else:
+        s.step_ps(ud, dt, 1, scheme, step0=2)
+    want = _oracle_step(model, u, dt, "heun" if scheme == "random" else scheme,
+                        alpha=oforcing.random_shift(12, 2))
+    _check(_host(ud), want, "fp64", scheme)
 
 
 def test_nonlinear_deterministic():
@@ -269,16 +303,18 @@ def test_energy_conservation_on_gpu():
         assert abs(spectra.inner(u, nh)) <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("n,ct", [(64, 1.0), (128, 1.0), (128, 2 / 3), (192, 2 / 3), (256, 1.0)])
-def test_specialised_passes_match_generic(n, ct):
+@pytest.mark.parametrize("n,ct,mask", [(64, 1.0, "sphere"), (128, 1.0, "sphere"), (128, 2 / 3, "sphere"),
+                                       (192, 2 / 3, "sphere"), (256, 1.0, "sphere"),
+                                       (128, 1.0, "no_multiple_aliases"), (128, 2 / 3, "cube")])
+def test_specialised_passes_match_generic(n, ct, mask):
     """The compile-time FP32 passes (N = 64, 128, 192, 256) and the size-generic passes
     agree to FP32 round-off (each is within ~5e-6 of the FP64 oracle), for the
     nonlinear term and two steps of every scheme."""
-    print(f"[fast-vs-generic] n={n} ct={ct:.4f}", flush=True)
+    print(f"[fast-vs-generic] n={n} ct={ct:.4f} mask={mask}", flush=True)
     nu, dt = 1 / 1600, 2e-3
-    fast = _solver(n, ct, nu=nu, seed=4)
-    gen = _solver(n, ct, nu=nu, seed=4, generic=True)
-    u = _rep(_field(n, ct, "sphere", 77, energy=0.5), "fp32")
+    fast = _solver(n, ct, mask, nu=nu, seed=4)
+    gen = _solver(n, ct, mask, nu=nu, seed=4, generic=True)
+    u = _rep(_field(n, ct, mask, 77, energy=0.5), "fp32")
     for shift in [None, (0.5, 0.5, 0.5), (0.3, 0.8, 0.45)]:
         a = _host(fast.nonlinear(fast.to_device(u), shift=shift))
         b = _host(gen.nonlinear(gen.to_device(u), shift=shift))
