@@ -100,14 +100,16 @@ struct FastCfg {
 };
 
 // ------------------------------------------------------------------ x inverse
-// One (tile, field) per block.  Blocks are dispatched round-robin over the 8
-// XCDs; block b works on tile 8 (b div 48) + (b mod 8) and field (b div 8) mod 6,
-// so the six blocks of a tile run back to back on one XCD and re-read the state
-// from its L2.  The tile list is padded to a multiple of 8 with empty tiles.
+// One active tile per block, all six fields.  Along an x line k_y and k_z are
+// fixed, so the x transform of omega_x = i (k_y u_z - k_z u_y) is
+// i k_y X(u_z) - i k_z X(u_y), and omega_y = i k_z u_x - i k_x u_z,
+// omega_z = i k_x u_y - i k_y u_x need only D_z = X(i k_x u_z) and D_y = X(i k_x u_y)
+// beside the velocity transforms: five transforms for six fields, and each state
+// component is read once per tile.
 template <typename C>
 __global__ void __launch_bounds__(kFastL * C::TPL)
 f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg,
-       Shift sh, const int2* __restrict__ tiles, Geom g) {
+        Shift sh, const int2* __restrict__ tiles, Geom g) {
   constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
   using F = RegFft<N, TPL, +1, typename C::Inv>;
   __shared__ Cx<float> tw[N];
@@ -116,9 +118,7 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   __shared__ Cx<float> xb[N * kFastLp];
   const int tid = threadIdx.x;
   const int l = tid % kFastL, t = tid / kFastL;
-  const int b = blockIdx.x;
-  const int f = (b >> 3) % 6;
-  const int2 tile = tiles[8 * (b / 48) + (b & 7)];
+  const int2 tile = tiles[blockIdx.x];
   const int yi = tile.x, kz0 = tile.y, kz = kz0 + l;
   const int ky = kval(yi, N);
   for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
@@ -131,54 +131,63 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
     phyz = phc[l];
   }
   const LineView<float, kFastLp> lv{xb + l};
-  // element (k_x index p, yi, kz) of a component: offset p N pitch + yi pitch + kz
   const uint32_t sbase = (uint32_t)(yi * ls.pitch + kz0) + l, sstep = (uint32_t)(N * ls.pitch);
-  // field f = sum_c coef_c(k) u_c: u_x, u_y, u_z, then omega = i k x u
-  const int c1 = (f < 3) ? f : (f == 3 ? 2 : (f == 4 ? 0 : 1));
-  const int c2 = (f == 3) ? 1 : (f == 4 ? 2 : 0);
-  const Cx<float>* S1 = S + c1 * ls.cs;
-  const Cx<float>* S2 = S + c2 * ls.cs;
   const float kyf = float(ky), kzf = float(kz);
-  Cx<float> v[EPT], a2[EPT];
-  bool ok[EPT];
-  uint32_t idx[EPT];
-  const LineTest keep = line_test(g, ky, col ? kz : 0);  // (padding tiles carry a huge kz)
+  Cx<float> ux[EPT], uy[EPT], uz[EPT], dy[EPT], dz[EPT];
+  {
+    bool ok[EPT];
+    uint32_t idx[EPT];
+    const LineTest keep = line_test(g, ky, kz);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = F::in_pos(t, i);
+      ok[i] = col && keep(kval(p, N));
+      idx[i] = (uint32_t)p * sstep + sbase;
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      ux[i] = ld_masked(S, idx[i], ok[i]);
+      uy[i] = ld_masked(S + ls.cs, idx[i], ok[i]);
+      uz[i] = ld_masked(S + 2 * ls.cs, idx[i], ok[i]);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int p = F::in_pos(t, i);
-    ok[i] = col && keep(kval(p, N));
-    idx[i] = (uint32_t)p * sstep + sbase;
-  }
-  // straight-line load loops (one per case) so that all loads issue before the first wait
-  if (f < 3) {
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) v[i] = ld_masked(S1, idx[i], ok[i]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      v[i] = ld_masked(S1, idx[i], ok[i]);
-      a2[i] = ld_masked(S2, idx[i], ok[i]);
+    if (sh.on) {
+      const Cx<float> phi = cmul(phx[p], phyz);
+      ux[i] = cmul(ux[i], phi);
+      uy[i] = cmul(uy[i], phi);
+      uz[i] = cmul(uz[i], phi);
     }
-    // omega_x = i(ky u_z - kz u_y), omega_y = i(kz u_x - kx u_z), omega_z = i(kx u_y - ky u_x)
+    const float kxf = float(kval(p, N));
+    dy[i] = mul_i(scale(uy[i], kxf));
+    dz[i] = mul_i(scale(uz[i], kxf));
+  }
+  const uint32_t obase = (uint32_t)(yi * g.kzp + kz0) + l, ostep = (uint32_t)(N * g.kzp);
+  auto store = [&](int f, const Cx<float>* v) {
+    if (col) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const float kxf = float(kval(F::in_pos(t, i), N));
-      const float w1 = (f == 3) ? kyf : (f == 4 ? kzf : kxf);
-      const float w2 = (f == 3) ? kzf : (f == 4 ? kxf : kyf);
-      v[i] = mul_i(scale(v[i], w1) - scale(a2[i], w2));
+      for (int i = 0; i < EPT; ++i) st_off(W + f * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
     }
-  }
-  if (sh.on) {
+  };
+  F::run(uy, t, lv, tw);
+  store(1, uy);
+  F::run(uz, t, lv, tw);
+  store(2, uz);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) v[i] = cmul(v[i], cmul(phx[F::in_pos(t, i)], phyz));
-  }
-  F::run(v, t, lv, tw);
-  if (col) {
-    Cx<float>* out = W + f * g.wcomp;
-    const uint32_t obase = (uint32_t)(yi * g.kzp + kz0) + l, ostep = (uint32_t)(N * g.kzp);
+  for (int i = 0; i < EPT; ++i) uy[i] = mul_i(scale(uz[i], kyf) - scale(uy[i], kzf));  // omega_x
+  store(3, uy);
+  F::run(ux, t, lv, tw);
+  store(0, ux);
+  F::run(dz, t, lv, tw);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) st_off(out, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
-  }
+  for (int i = 0; i < EPT; ++i) dz[i] = mul_i(scale(ux[i], kzf)) - dz[i];  // omega_y
+  store(4, dz);
+  F::run(dy, t, lv, tw);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) dy[i] = dy[i] - mul_i(scale(ux[i], kyf));  // omega_z
+  store(5, dy);
 }
 
 // ------------------------------------------------------------------ y passes (in place)

@@ -73,7 +73,7 @@ struct Layout {
   int pa, ta;        // the same for the adjoint z pass (0: adjoint not available)
   long long k2top;   // largest retained |k|^2
   int nsh, nbins;
-  std::vector<int2> tiles;   // active (k_y index, k_z tile start), padded to a multiple of 8
+  std::vector<int2> tiles;   // active (k_y index, k_z tile start)
   int ntiles_active;
   size_t off_tw, off_etab, off_force, off_tiles, off_w, off_s, off_a, off_spec, off_specout;
   size_t total;
@@ -196,7 +196,6 @@ bool make_layout(const ns_config* c, Layout* lay) {
     }
   }
   lay->ntiles_active = (int)lay->tiles.size();
-  while (lay->tiles.size() % 8 != 0) lay->tiles.push_back(make_int2(0, 1 << 20));
   lay->nsh = num_shells(n);
   lay->nbins = 3 * lay->nsh + 3 * g.h + 5;
   // workspace
@@ -352,9 +351,8 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift
   hipError_t e;
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
-    const int padded = (ntiles + 7) / 8 * 8;
     if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(6 * padded), dim3(ns::kFastL * C::XInv::TPL), 0,
+    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
                        c->stream, in, lin, p.W, p.tw, sh, p.tiles, g);
     if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
