@@ -344,6 +344,36 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   const LineView<float, kFastLp> lv{xb + l};
   Cx<float> r[3][EPT];
   Cx<float> phyz = cx(1.f, 0.f);
+  // stage operands, read per chunk of points before that chunk's stores (out0 may
+  // alias an operand, which keeps the compiler from hoisting loads above stores):
+  // all points for one-operand stages, half of them for two-operand ones; the first
+  // chunk is read before the last transform so that its latency overlaps it
+  constexpr bool need0 = (OP == OP_HEUN1 || OP == OP_EX1B || OP == OP_EX2B || OP == OP_RK4_0 ||
+                          OP == OP_RK4_1 || OP == OP_RK4_2);
+  constexpr bool need1 = (OP == OP_AVG || OP == OP_HEUN2 || OP == OP_EX1B || OP == OP_EX2B ||
+                          OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3);
+  constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
+  constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
+  const LineTest keep = line_test(g, ky, kz);
+  const bool line_kept = active && kz < g.kzn;
+  Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];
+  auto load_ops = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int p = F::out_pos(t, c0 + j);
+      const bool ok = line_kept && keep(kval(p, N));
+      if constexpr (need0) {
+        const uint32_t ii0 = (uint32_t)((p * N + yi) * a.li0.pitch + kz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s0v[c][j] = ld_masked(a.in0 + c * a.li0.cs, ii0, ok);
+      }
+      if constexpr (need1) {
+        const uint32_t ii1 = (uint32_t)((p * N + yi) * a.li1.pitch + kz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s1v[c][j] = ld_masked(a.in1 + c * a.li1.cs, ii1, ok);
+      }
+    }
+  };
   if (active) {
     for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
     if (sh.on) {
@@ -361,6 +391,8 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
           r[f + 1][i] = ld_masked(W + (f + 1) * g.wcomp, (uint32_t)F::in_pos(t, i) * wstep + wbase, col);
+      } else {
+        load_ops(0);
       }
       F::run(r[f], t, lv, tw);  // its barriers also publish phx and phc
     }
@@ -368,35 +400,9 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   }
   if (kz >= g.h || (!a.full && kz >= g.kzn)) return;
   const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
-  // stage operands, loaded for a chunk of points before that chunk's stores (out0
-  // may alias an operand, which keeps the compiler from hoisting loads above
-  // stores): all points for one-operand stages, half of them for two-operand ones
-  constexpr bool need0 = (OP == OP_HEUN1 || OP == OP_EX1B || OP == OP_EX2B || OP == OP_RK4_0 ||
-                          OP == OP_RK4_1 || OP == OP_RK4_2);
-  constexpr bool need1 = (OP == OP_AVG || OP == OP_HEUN2 || OP == OP_EX1B || OP == OP_EX2B ||
-                          OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3);
-  constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
-  constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
-  const LineTest keep = line_test(g, ky, kz);
-  const bool line_kept = active && kz < g.kzn;
 #pragma unroll
   for (int c0 = 0; c0 < EPT; c0 += CH) {
-  Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];
-#pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    const int p = F::out_pos(t, c0 + j);
-    const bool ok = line_kept && keep(kval(p, N));
-    if constexpr (need0) {
-      const uint32_t ii0 = (uint32_t)((p * N + yi) * a.li0.pitch + kz);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) s0v[c][j] = ld_masked(a.in0 + c * a.li0.cs, ii0, ok);
-    }
-    if constexpr (need1) {
-      const uint32_t ii1 = (uint32_t)((p * N + yi) * a.li1.pitch + kz);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) s1v[c][j] = ld_masked(a.in1 + c * a.li1.cs, ii1, ok);
-    }
-  }
+  if (c0 > 0 || !active) load_ops(c0);
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int i = c0 + j;
