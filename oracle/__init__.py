@@ -18,6 +18,7 @@ schemes    integrating-factor Euler, midpoint RK2, Lawson RK4, phase-shifted RK2
            (exact / approx / random, optional split forcing) and the step adjoint
 spectra    shell, 1D, dissipation and transfer spectra; totals
 forcing    SplitMix64 counter-based draws, forcing amplitudes and injection scaling
+quality    error index of a run's 1D spectra against a reference run
 nl1d       the 1D quadratic model dS/dt = -S^2
 
 Parity status: every function is pinned by at least one test in

@@ -528,3 +528,27 @@ def test_forcing_shape_and_unit_injection():
     u0 = inputs.hit_initial(n, 3, grid.sphere_k2max(n, 1.0))
     o = forcing.forcing(u0, dt, 5, 17)
     assert abs(spectra.energy(u0 + dt * o) - spectra.energy(u0) - dt) < 1e-13
+
+
+# ----------------------------------------------------------------------------- error index
+def test_error_index_closed_forms():
+    """Eq. quality-i-disc: zero for identical spectra, 100 |c| for E = (1 + c) E_ref in
+    every bin, and for a single perturbed bin the 1/k weight over N_t sum 1/k."""
+    from oracle import quality
+    rng = np.random.default_rng(3)
+    ref = [rng.random((3, 20)) + 0.1 for _ in range(4)]
+    assert quality.error_index(ref, ref, 15)[0] == 0.0
+    for c in (0.1, -0.03):
+        run = [(1 + c) * r for r in ref]
+        tot, dirs = quality.error_index(run, ref, 15)
+        assert abs(tot - 100 * abs(c)) < 1e-12 and all(abs(d - 100 * abs(c)) < 1e-12 for d in dirs)
+    run = [r.copy() for r in ref]
+    run[2][1][5] *= 1.2                       # direction y, sample 2, k = 5: +20 %
+    tot, dirs = quality.error_index(run, ref, 15)
+    want = (1 / 5) * 20.0 / (4 * sum(1.0 / n for n in range(1, 16)))
+    assert abs(dirs[1] - want) < 1e-12 and dirs[0] == 0 and dirs[2] == 0
+    assert abs(tot - want / 3) < 1e-12
+    # bins above kmax and the k = 0 bin do not count
+    run[0][0][0] *= 5
+    run[0][0][16] *= 5
+    assert abs(quality.error_index(run, ref, 15)[0] - want / 3) < 1e-12
