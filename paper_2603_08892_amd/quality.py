@@ -1,0 +1,120 @@
+"""Accuracy against cost on the GPU: Taylor-Green runs of each scheme at matched
+k_max, their 1D energy spectra through the transition, and the spectral error
+index of Sec. "Performance and accuracy for a decaying flow" (Eq. quality; its
+discrete form in the appendix, with the wavenumber sum starting at k = 1)
+against a dealiased reference run.
+
+    python -m paper_2603_08892_amd.quality [--t-start 7 --t-end 12 --every 0.1]
+
+prints one JSON object: per run the grid, truncation, error index (percent),
+wall time and speedup over the reference (at equal dt, and under the paper's
+CFL protocol: CFL 0.4 for the RK2 schemes and 1.0 for RK4, dt proportional to
+the grid spacing).
+"""
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, ns
+
+NU, DT = 1.0 / 1600.0, 2e-3
+KMAX = 63                      # largest |k_i| retained with k^2 <= 4095
+
+# name: (scheme, N, C_t, CFL number of the scheme)
+RUNS = {
+    "rk4_192_reference": ("rk4", 192, 2.0 / 3.0, 1.0),
+    "ps_random_128": ("random", 128, 1.0, 0.4),
+    "ps_approx_128": ("approx", 128, 1.0, 0.4),
+    "ps_exact_128": ("exact", 128, 1.0, 0.4),
+    "rk4_128_aliased": ("rk4", 128, 1.0, 1.0),
+}
+REFERENCE = "rk4_192_reference"
+
+
+def error_index(e1d, e1d_ref, kmax):
+    """Mean over the three directions of the time- and 1/k-weighted mean of
+    100 |E_ref - E| / E_ref over the 1D wavenumbers 1..kmax.
+    e1d, e1d_ref: arrays [samples, 3, >= kmax + 1]."""
+    e = np.asarray(e1d, dtype=np.float64)[:, :, 1:kmax + 1]
+    r = np.asarray(e1d_ref, dtype=np.float64)[:, :, 1:kmax + 1]
+    if e.shape != r.shape or e.shape[0] == 0:
+        raise ValueError("need the same, non-zero number of samples in both runs")
+    if not np.all(r > 0):
+        raise ValueError("the reference spectra have empty bins in 1..kmax")
+    w = 1.0 / np.arange(1, kmax + 1)
+    rel = 100.0 * np.abs(r - e) / r
+    per_dir = (rel * w).sum(axis=(0, 2)) / (e.shape[0] * w.sum())
+    return float(per_dir.mean()), per_dir.tolist()
+
+
+def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=2026, kmax=KMAX):
+    """Time-step the Taylor-Green field to t_end; returns the sample times, the 1D
+    spectra [samples, 3, kmax + 1] taken every `every` time units from t_start, and
+    the wall time of the whole run (stepping and sampling)."""
+    import torch
+    s = ns.Solver(n, nu, ct, precision="fp32", seed=seed)
+    u = s.to_device(inputs.taylor_green(n))
+    nsteps = int(round(t_end / dt))
+    first, stride = int(round(t_start / dt)), max(1, int(round(every / dt)))
+    times, spec = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nsteps):
+        if scheme == "rk4":
+            s.step_rk4(u, dt, 1)
+        elif scheme in ("exact", "approx"):
+            s.step_ps(u, dt, 1, scheme)
+        else:
+            s.step_ps(u, dt, 1, "random", step0=i)
+        k = i + 1
+        if k >= first and (k - first) % stride == 0:
+            spec.append(s.spectra(u)["e_1d"][:, :kmax + 1].copy())
+            times.append(k * dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return np.array(times), np.array(spec), wall
+
+
+def compare(t_start, t_end, every, runs=None, log=sys.stderr):
+    runs = list(RUNS) if runs is None else runs
+    if REFERENCE not in runs:
+        runs = [REFERENCE] + runs
+    out = {}
+    for name in runs:
+        scheme, n, ct, _ = RUNS[name]
+        tt, sp, wall = run_taylor_green(scheme, n, ct, t_start, t_end, every)
+        out[name] = {"scheme": scheme, "n": n, "ct": round(ct, 6), "wall_s": wall, "times": tt, "spec": sp}
+        print(f"[quality] {name}: {len(tt)} samples, {wall:.2f} s", file=log, flush=True)
+    ref = out[REFERENCE]
+    _, nr, _, cfl_r = RUNS[REFERENCE]
+    rows = {}
+    for name, r in out.items():
+        _, n, _, cfl = RUNS[name]
+        err, dirs = error_index(r["spec"], ref["spec"], KMAX)
+        eq = ref["wall_s"] / r["wall_s"]
+        # CFL protocol: dt = CFL dx / U, so the ratio of step counts is (cfl n_ref) / (cfl_ref n)
+        rows[name] = {"scheme": r["scheme"], "n": n, "ct": r["ct"], "error_pct": round(err, 4),
+                      "error_pct_xyz": [round(d, 4) for d in dirs], "wall_s": round(r["wall_s"], 4),
+                      "speedup_equal_dt": round(eq, 3),
+                      "speedup_cfl_protocol": round(eq * (cfl * nr) / (cfl_r * n), 3)}
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--t-start", type=float, default=7.0)
+    ap.add_argument("--t-end", type=float, default=12.0)
+    ap.add_argument("--every", type=float, default=0.1)
+    args = ap.parse_args()
+    rows = compare(args.t_start, args.t_end, args.every)
+    print(json.dumps({"workload": f"Taylor-Green nu=1/1600 dt={DT} t in [{args.t_start}, {args.t_end}], "
+                                  f"k_max=64 (k^2 <= 4095), 1D spectra every {args.every}",
+                      "reference": REFERENCE, "runs": rows}))
+
+
+if __name__ == "__main__":
+    main()
