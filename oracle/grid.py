@@ -62,22 +62,19 @@ def cube_kmax(n, ct):
     return largest_int_below(ct * n / 2.0)
 
 
-def double_alias_reach(n, k2max):
-    """Modes k that a double alias can reach when every input has |k|^2 <= k2max.
+def double_alias_free(n):
+    """Modes with |k_i| + |k_j| < 2N/3 for every pair of axes.
 
     A double alias on the axes (i, j) adds to k the products of input pairs with
     k_n + k_m = k + N (s_i e_i + s_j e_j) (Sec. "Extension to the multidimensional
-    case": two components of the nonlinear wavevector out of range).  Such a pair
-    exists only if |k + N (s_i e_i + s_j e_j)| <= 2 sqrt(k2max) (triangle
-    inequality); the image nearest the origin has components N - |k_i|, N - |k_j|
-    and k_l, so k is reachable when (N - |k_i|)^2 + (N - |k_j|)^2 + k_l^2 <= 4 k2max
-    for some pair.  A triple-alias image is farther out on every axis, so the
-    triple aliases are inside this set.
+    case": two components of the nonlinear wavevector out of range), so
+    |q_i| + |q_j| >= 2N - |k_i| - |k_j| for q = k_n + k_m.  If every input and the
+    output keep |k_i| + |k_j| < 2N/3, then |q_i| + |q_j| < 4N/3 < 2N - |k_i| - |k_j|:
+    a state held in this set never receives a double (or triple) alias.
     """
     kx, ky, kz = kgrid(n)
-    a, b, c = n - np.abs(kx), n - np.abs(ky), n - np.abs(kz)
-    k4 = 4 * k2max
-    return (a * a + b * b + kz * kz <= k4) | (a * a + c * c + ky * ky <= k4) | (b * b + c * c + kx * kx <= k4)
+    a, b, c = np.abs(kx), np.abs(ky), np.abs(kz)
+    return (3 * (a + b) < 2 * n) & (3 * (a + c) < 2 * n) & (3 * (b + c) < 2 * n)
 
 
 def mask(n, ct, kind="sphere"):
@@ -85,10 +82,9 @@ def mask(n, ct, kind="sphere"):
 
     sphere: keep |k| < C_t k_N (Fig. 1b, parameterised by C_t with k_max = C_t k_N);
     cube:   keep max_i |k_i| < C_t k_N (Fig. 1a);
-    no_multiple_aliases: the sphere without the modes double aliases can reach
-            (Fig. 7b; the paper shows the regions but gives no formula, so the
-            region is the reachable set of double_alias_reach with the sphere's
-            inputs).  For C_t <= 2 sqrt(2)/3 nothing is removed.
+    no_multiple_aliases: the sphere intersected with double_alias_free (Fig. 7b;
+            the paper draws the regions but gives no formula).  For
+            C_t <= 2 sqrt(2)/3 the sphere lies inside and nothing is removed.
     """
     if kind == "sphere":
         return k2grid(n) <= sphere_k2max(n, ct)
@@ -97,8 +93,7 @@ def mask(n, ct, kind="sphere"):
         km = cube_kmax(n, ct)
         return (np.abs(kx) <= km) & (np.abs(ky) <= km) & (np.abs(kz) <= km)
     if kind == "no_multiple_aliases":
-        k2max = sphere_k2max(n, ct)
-        return (k2grid(n) <= k2max) & ~double_alias_reach(n, k2max)
+        return (k2grid(n) <= sphere_k2max(n, ct)) & double_alias_free(n)
     raise ValueError(kind)
 
 

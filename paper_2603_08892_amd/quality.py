@@ -4,7 +4,7 @@ index of Sec. "Performance and accuracy for a decaying flow" (Eq. quality; its
 discrete form in the appendix, with the wavenumber sum starting at k = 1)
 against a dealiased reference run.
 
-    python -m paper_2603_08892_amd.quality [--t-start 7 --t-end 12 --every 0.1]
+    python -m paper_2603_08892_amd.quality [--t-start 7 --t-end 12 --every 0.1] [--sweep]
 
 prints one JSON object: per run the grid, truncation, error index (percent),
 wall time and speedup over the reference (at equal dt, and under the paper's
@@ -24,13 +24,23 @@ from . import inputs, ns
 NU, DT = 1.0 / 1600.0, 2e-3
 KMAX = 63                      # largest |k_i| retained with k^2 <= 4095
 
-# name: (scheme, N, C_t, CFL number of the scheme)
+# name: (scheme, N, C_t, CFL number of the scheme, mask); every run keeps k^2 <= 4095
 RUNS = {
-    "rk4_192_reference": ("rk4", 192, 2.0 / 3.0, 1.0),
-    "ps_random_128": ("random", 128, 1.0, 0.4),
-    "ps_approx_128": ("approx", 128, 1.0, 0.4),
-    "ps_exact_128": ("exact", 128, 1.0, 0.4),
-    "rk4_128_aliased": ("rk4", 128, 1.0, 1.0),
+    "rk4_192_reference": ("rk4", 192, 2.0 / 3.0, 1.0, "sphere"),
+    "ps_random_128": ("random", 128, 1.0, 0.4, "sphere"),
+    "ps_approx_128": ("approx", 128, 1.0, 0.4, "sphere"),
+    "ps_exact_128": ("exact", 128, 1.0, 0.4, "sphere"),
+    "rk4_128_aliased": ("rk4", 128, 1.0, 1.0, "sphere"),
+}
+# the truncation sweep at the same k_max (the grids of Table S1 scaled to k_max = 64):
+# C_t = 128 / N, and the "no_multiple_aliases" truncation at C_t = 1 (Fig. 7b)
+SWEEP = {
+    "ps_random_128_nma": ("random", 128, 1.0, 0.4, "no_multiple_aliases"),
+    "ps_exact_128_nma": ("exact", 128, 1.0, 0.4, "no_multiple_aliases"),
+    "ps_random_144": ("random", 144, 128 / 144, 0.4, "sphere"),
+    "ps_exact_144": ("exact", 144, 128 / 144, 0.4, "sphere"),
+    "ps_random_160": ("random", 160, 0.8, 0.4, "sphere"),
+    "ps_exact_160": ("exact", 160, 0.8, 0.4, "sphere"),
 }
 REFERENCE = "rk4_192_reference"
 
@@ -51,12 +61,12 @@ def error_index(e1d, e1d_ref, kmax):
     return float(per_dir.mean()), per_dir.tolist()
 
 
-def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=2026, kmax=KMAX):
+def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=2026, kmax=KMAX, mask="sphere"):
     """Time-step the Taylor-Green field to t_end; returns the sample times, the 1D
     spectra [samples, 3, kmax + 1] taken every `every` time units from t_start, and
     the wall time of the whole run (stepping and sampling)."""
     import torch
-    s = ns.Solver(n, nu, ct, precision="fp32", seed=seed)
+    s = ns.Solver(n, nu, ct, mask=mask, precision="fp32", seed=seed)
     u = s.to_device(inputs.taylor_green(n))
     nsteps = int(round(t_end / dt))
     first, stride = int(round(t_start / dt)), max(1, int(round(every / dt)))
@@ -80,24 +90,26 @@ def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=20
 
 
 def compare(t_start, t_end, every, runs=None, log=sys.stderr):
+    table = {**RUNS, **SWEEP}
     runs = list(RUNS) if runs is None else runs
     if REFERENCE not in runs:
         runs = [REFERENCE] + runs
     out = {}
     for name in runs:
-        scheme, n, ct, _ = RUNS[name]
-        tt, sp, wall = run_taylor_green(scheme, n, ct, t_start, t_end, every)
-        out[name] = {"scheme": scheme, "n": n, "ct": round(ct, 6), "wall_s": wall, "times": tt, "spec": sp}
+        scheme, n, ct, _, mask = table[name]
+        tt, sp, wall = run_taylor_green(scheme, n, ct, t_start, t_end, every, mask=mask)
+        out[name] = {"scheme": scheme, "n": n, "ct": round(ct, 6), "mask": mask, "wall_s": wall, "times": tt,
+                     "spec": sp}
         print(f"[quality] {name}: {len(tt)} samples, {wall:.2f} s", file=log, flush=True)
     ref = out[REFERENCE]
-    _, nr, _, cfl_r = RUNS[REFERENCE]
+    _, nr, _, cfl_r, _ = table[REFERENCE]
     rows = {}
     for name, r in out.items():
-        _, n, _, cfl = RUNS[name]
+        _, n, _, cfl, _ = table[name]
         err, dirs = error_index(r["spec"], ref["spec"], KMAX)
         eq = ref["wall_s"] / r["wall_s"]
         # CFL protocol: dt = CFL dx / U, so the ratio of step counts is (cfl n_ref) / (cfl_ref n)
-        rows[name] = {"scheme": r["scheme"], "n": n, "ct": r["ct"], "error_pct": round(err, 4),
+        rows[name] = {"scheme": r["scheme"], "n": n, "ct": r["ct"], "mask": r["mask"], "error_pct": round(err, 4),
                       "error_pct_xyz": [round(d, 4) for d in dirs], "wall_s": round(r["wall_s"], 4),
                       "speedup_equal_dt": round(eq, 3),
                       "speedup_cfl_protocol": round(eq * (cfl * nr) / (cfl_r * n), 3)}
@@ -109,8 +121,9 @@ def main():
     ap.add_argument("--t-start", type=float, default=7.0)
     ap.add_argument("--t-end", type=float, default=12.0)
     ap.add_argument("--every", type=float, default=0.1)
+    ap.add_argument("--sweep", action="store_true", help="also the truncation sweep at the same k_max")
     args = ap.parse_args()
-    rows = compare(args.t_start, args.t_end, args.every)
+    rows = compare(args.t_start, args.t_end, args.every, list(RUNS) + (list(SWEEP) if args.sweep else []))
     print(json.dumps({"workload": f"Taylor-Green nu=1/1600 dt={DT} t in [{args.t_start}, {args.t_end}], "
                                   f"k_max=64 (k^2 <= 4095), 1D spectra every {args.every}",
                       "reference": REFERENCE, "runs": rows}))
