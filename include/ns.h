@@ -71,10 +71,9 @@ typedef enum { NS_FP32 = 0, NS_FP64 = 1 } ns_precision;
 /* Truncation masks (Sec. "Standard dealiasing with truncation", Figs. 1 and 7):
  * SPHERE keeps |k| < C_t N/2, i.e. |k|^2 <= K2max (the largest integer below
  * (C_t N/2)^2); CUBE keeps every |k_i| < C_t N/2; NO_MULTIPLE_ALIASES keeps the
- * sphere minus the modes a double alias can reach from two inputs of the sphere:
- * k is removed when, for some pair of axes (i, j) with third axis l,
- * (N - |k_i|)^2 + (N - |k_j|)^2 + k_l^2 <= 4 K2max (identical to SPHERE for
- * C_t <= 2 sqrt(2)/3; Fig. 7b at C_t = 1). */
+ * modes of the sphere with |k_i| + |k_j| < 2N/3 for every pair of axes, so that
+ * no double (or triple) alias of a state held in it reaches a kept mode
+ * (identical to SPHERE for C_t <= 2 sqrt(2)/3; Fig. 7b at C_t = 1). */
 typedef enum { NS_MASK_SPHERE = 0, NS_MASK_CUBE = 1, NS_MASK_NO_MULTIPLE_ALIASES = 2 } ns_mask;
 
 /* Phase-shift RK2 variants (Sec. "Extension to the multidimensional case"). */

@@ -43,30 +43,25 @@ __device__ __forceinline__ Cx<float> ld_masked(const Cx<float>* __restrict__ bas
 }
 
 // Truncation test along one k_x line (fixed k_y, k_z) in 32-bit arithmetic
-// (|k_i| <= N/2 <= 128 here): every mask is k_x^2 <= hi2, and for the
-// no-multiple-aliases mask also lo2 < k_x^2 and (N - |k_x|)^2 > ah2, with
-// per-line thresholds.
+// (|k_i| <= N/2 <= 128 here): every mask is k_x^2 <= hi2 and |k_x| <= xmax with
+// per-line thresholds (xmax from the pair conditions of double_alias_free).
 struct LineTest {
-  int hi2, lo2, ah2, n;
-  bool alias;  // the double-alias thresholds apply (block-uniform)
+  int hi2, xmax;
   __device__ __forceinline__ bool operator()(int kx) const {
     // evaluated without short-circuit branches, so masked loads stay unconditional
-    const int k2 = kx * kx, a = n - abs(kx);
-    return (k2 <= hi2) & (!alias | ((k2 > lo2) & (a * a > ah2)));
+    return (kx * kx <= hi2) & (abs(kx) <= xmax);
   }
 };
 __device__ __forceinline__ LineTest line_test(const Geom& g, int ky, int kz) {
-  LineTest L{0, -1, -1, g.n, g.mask == 2};
+  LineTest L{0, g.n};
   if (g.mask == 1) {
     L.hi2 = (abs(ky) <= g.kmax && kz <= g.kmax) ? g.kmax * g.kmax : -1;
   } else {
-    const int k2 = (int)g.k2max;
-    L.hi2 = k2 - ky * ky - kz * kz;
+    L.hi2 = (int)g.k2max - ky * ky - kz * kz;
     if (g.mask == 2) {
-      // no double alias on (x, y), (x, z) or (y, z): see double_alias_free
-      const int b = g.n - abs(ky), c = g.n - abs(kz);
-      L.lo2 = 4 * k2 - b * b - c * c;
-      L.ah2 = max(4 * k2 - b * b - kz * kz, 4 * k2 - c * c - ky * ky);
+      // 3 (|k_x| + |k_y|) < 2N, 3 (|k_x| + |k_z|) < 2N and 3 (|k_y| + |k_z|) < 2N
+      const int b = abs(ky), c = abs(kz), n2 = 2 * g.n;
+      L.xmax = (3 * (b + c) < n2) ? (n2 - 1) / 3 - max(b, c) : -1;
     }
   }
   return L;

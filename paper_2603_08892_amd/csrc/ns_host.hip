@@ -83,8 +83,8 @@ bool retained_host(const Geom& g, long long kx, long long ky, long long kz) {
   if (g.mask == 1) return std::llabs(kx) <= g.kmax && std::llabs(ky) <= g.kmax && kz <= g.kmax;
   if (kx * kx + ky * ky + kz * kz > g.k2max) return false;
   if (g.mask == 0) return true;
-  const long long a = g.n - std::llabs(kx), b = g.n - std::llabs(ky), c = g.n - std::llabs(kz), k4 = 4 * g.k2max;
-  return a * a + b * b + kz * kz > k4 && a * a + c * c + ky * ky > k4 && b * b + c * c + kx * kx > k4;
+  const long long a = std::llabs(kx), b = std::llabs(ky), c = std::llabs(kz), n2 = 2LL * g.n;
+  return 3 * (a + b) < n2 && 3 * (a + c) < n2 && 3 * (b + c) < n2;
 }
 
 int kval_host(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }

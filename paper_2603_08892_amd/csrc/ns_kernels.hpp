@@ -35,13 +35,12 @@ struct Geom {
 
 __device__ __forceinline__ int kval(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
-// No double alias reaches k from two inputs with |k|^2 <= K2max: for every pair of
-// axes the image of k nearest the origin, (N - |k_i|, N - |k_j|, k_l), is longer
-// than 2 sqrt(K2max).
+// |k_i| + |k_j| < 2N/3 for every pair of axes: a state held in this set never
+// receives a double alias (a pair sum reaching k + N(s_i e_i + s_j e_j) would need
+// |q_i| + |q_j| >= 2N - |k_i| - |k_j| > 4N/3, more than two such modes can add up to).
 __device__ __forceinline__ bool double_alias_free(const Geom& g, int kx, int ky, int kz) {
-  const long long a = g.n - abs(kx), b = g.n - abs(ky), c = g.n - abs(kz), k4 = 4 * g.k2max;
-  return a * a + b * b + (long long)kz * kz > k4 && a * a + c * c + (long long)ky * ky > k4 &&
-         b * b + c * c + (long long)kx * kx > k4;
+  const int a = abs(kx), b = abs(ky), c = abs(kz), n2 = 2 * g.n;
+  return 3 * (a + b) < n2 && 3 * (a + c) < n2 && 3 * (b + c) < n2;
 }
 
 __device__ __forceinline__ bool retained(const Geom& g, int kx, int ky, int kz) {
