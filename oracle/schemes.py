@@ -36,13 +36,18 @@ def euler_ps(model, s0, dt):
     return model.E(dt) * (s0 + dt * na)
 
 
-def rk2(model, s0, dt, avg=False):
+def rk2(model, s0, dt, avg=False, shifts=None):
     """Midpoint RK2: stage 1 tau = dt/2 with N0, stage 2 tau = dt with N(S1).
-    With avg=True every evaluation is the two-shift average ("RK2 phase-shift exact")."""
+    With avg=True every evaluation is the two-shift average ("RK2 phase-shift exact");
+    `shifts` (a list of shift vectors) makes it the average over those shifts instead."""
+    if shifts is None:
+        shifts = [model.zero, model.half] if avg else [model.zero]
+
     def a(s):
-        if avg:
-            return 0.5 * (model.nl(s, model.zero) + model.nl(s, model.half))
-        return model.nl(s, model.zero)
+        acc = 0
+        for sh in shifts:
+            acc = acc + model.nl(s, sh)
+        return acc / len(shifts)
     h = 0.5 * dt
     eh = model.E(h)
     sh = eh * (s0 + h * a(s0))
@@ -52,6 +57,14 @@ def rk2(model, s0, dt, avg=False):
 def ps_exact(model, s0, dt):
     """RK2 phase-shift exact (midpoint RK2 with the two-shift average at both stages)."""
     return rk2(model, s0, dt, avg=True)
+
+
+def ps_exact8(model, s0, dt):
+    """Midpoint RK2 with every evaluation averaged over the eight shifts {0, 1/2}^3
+    (the fully exact 3D shift of Sec. "Extension to the multidimensional case":
+    it removes every alias class, double ones included)."""
+    eight = [(a, b, c) for a in (0.0, 0.5) for b in (0.0, 0.5) for c in (0.0, 0.5)]
+    return rk2(model, s0, dt, shifts=eight)
 
 
 def rk4(model, s0, dt):

@@ -279,7 +279,8 @@ def test_p7_exact_decay_every_scheme():
     want = np.exp(-nu * 4 * dt) * u0
     outs = [schemes.rk4(model, u0, dt), schemes.ps_exact(model, u0, dt),
             schemes.ps_heun(model, u0, dt, (0, 0, 0)), schemes.ps_heun(model, u0, dt, (0.3, 0.6, 0.1)),
-            schemes.rk2(model, u0, dt), schemes.euler(model, u0, dt)]
+            schemes.rk2(model, u0, dt), schemes.euler(model, u0, dt), schemes.euler_ps(model, u0, dt),
+            schemes.ps_exact8(model, u0, dt)]
     for o in outs:
         assert np.abs(o - want).max() < 1e-15
 
@@ -328,6 +329,24 @@ def test_p8_p12_1d_aliased():
     heun = lambda mo, s, dt: schemes.ps_heun(mo, s, dt, 0.0, 0.5)  # noqa: E731
     sl, _ = _slope(model, heun, lambda dt: heun(clean, s0, dt), dts, s0)
     assert abs(sl - 2) < 0.1, sl
+
+
+def test_p3_eight_shift_rk2_and_euler_ps_steps_are_clean():
+    """Step forms of P3 on a seeded field, N = 12: midpoint RK2 with every evaluation
+    averaged over the eight shifts {0, 1/2}^3 equals midpoint RK2 with the alias-free
+    (padded) product at C_t = 1, where the two-shift scheme keeps the double aliases;
+    Euler with the two-shift average (Eq. sum_ps_non_ps) equals alias-free Euler at
+    C_t = 0.9 < 2 sqrt(2)/3, where plain Euler does not."""
+    n, nu, dt = 12, 0.05, 0.05
+    for ct, shifted, plain, ref in ((1.0, schemes.ps_exact8, schemes.ps_exact, schemes.rk2),
+                                    (0.9, schemes.euler_ps, schemes.euler, schemes.euler)):
+        m = grid.mask(n, ct)
+        model, clean = onl.NSModel(n, nu, m), onl.NSModel(n, nu, m, clean=True)
+        u = inputs.random_solenoidal(n, 3, grid.sphere_k2max(n, ct))
+        want = ref(clean, u, dt)
+        scale = np.abs(want).max()
+        assert np.abs(shifted(model, u, dt) - want).max() < 1e-13 * scale, shifted.__name__
+        assert np.abs(plain(model, u, dt) - want).max() > 1e-2 * scale, plain.__name__
 
 
 # ----------------------------------------------------------------------------- P9
