@@ -85,6 +85,9 @@ def mask(n, ct, kind="sphere"):
     no_multiple_aliases: the sphere intersected with double_alias_free (Fig. 7b;
             the paper draws the regions but gives no formula).  For
             C_t <= 2 sqrt(2)/3 the sphere lies inside and nothing is removed.
+    rogallo: the cube intersected with double_alias_free: Rogallo's truncation,
+            which removes only the double aliases, the cube less thin prisms along
+            its edges (Fig. 5; the same reading of the removed regions).
     """
     if kind == "sphere":
         return k2grid(n) <= sphere_k2max(n, ct)
@@ -94,6 +97,8 @@ def mask(n, ct, kind="sphere"):
         return (np.abs(kx) <= km) & (np.abs(ky) <= km) & (np.abs(kz) <= km)
     if kind == "no_multiple_aliases":
         return (k2grid(n) <= sphere_k2max(n, ct)) & double_alias_free(n)
+    if kind == "rogallo":
+        return mask(n, ct, "cube") & double_alias_free(n)
     raise ValueError(kind)
 
 

@@ -178,6 +178,33 @@ def test_p3_no_multiple_aliases_mask_leaves_no_double_alias(n, ct):
     assert rel(onl.nonlinear_ps(us, sph), onl.nonlinear_pad(us, sph)) > 1e-6
 
 
+@pytest.mark.parametrize("n", [12, 16])
+def test_p3_rogallo_truncation_leaves_no_double_alias(n):
+    """Rogallo's truncation (Fig. 5) at C_t = 1: the cube less prisms along its twelve
+    edges (a mode goes iff two of its |k_i| add up to 2N/3 or more, so every removed
+    mode has two components above N/6 and lies outside the sphere |k| < 2 sqrt(2)/3 k_N);
+    with the state inside it every double- and triple-alias class is zero on the kept
+    modes and the isotropic pair average equals the padded product, while the full cube
+    does receive double aliases."""
+    m = grid.mask(n, 1.0, "rogallo")
+    cube = grid.mask(n, 1.0, "cube")
+    kx, ky, kz = grid.kgrid(n)
+    gone = cube & ~m
+    assert gone.any() and np.all(cube[m])
+    a = np.sort(np.stack(np.broadcast_arrays(np.abs(kx), np.abs(ky), np.abs(kz))), axis=0)
+    assert np.all(3 * (a[1] + a[2])[gone] >= 2 * n) and np.all(3 * (a[1] + a[2])[m] < 2 * n)
+    assert np.all(6 * a[1][gone] > n) and np.all(9 * grid.k2grid(n)[gone] >= 2 * n * n)
+    k2c = 3 * grid.cube_kmax(n, 1.0) ** 2
+    uh = inputs.random_solenoidal(n, 90 + n, k2c) * m
+    cls = _alias_classes(uh, n)
+    for e, c in cls.items():
+        if sum(abs(v) for v in e) >= 2:
+            assert np.abs(c[:, m]).max() < 1e-13, e
+    assert rel(onl.nonlinear_ps(uh, m), onl.nonlinear_pad(uh, m)) < 1e-13
+    uc = inputs.random_solenoidal(n, 95 + n, k2c) * cube
+    assert rel(onl.nonlinear_ps(uc, cube), onl.nonlinear_pad(uc, cube)) > 1e-6
+
+
 def test_p3_no_multiple_aliases_equals_sphere_below_2sqrt2_over_3():
     """Spherical truncation at C_t <= 2 sqrt(2)/3 already removes every double alias
     (Patterson and Orszag, cited in Sec. "Extension to the multidimensional case"), so
