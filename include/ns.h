@@ -68,19 +68,35 @@ typedef enum {
 } ns_status;
 
 typedef enum { NS_FP32 = 0, NS_FP64 = 1 } ns_precision;
-/* Truncation masks (Sec. "Standard dealiasing with truncation", Figs. 1 and 7):
+/* Truncation masks (Sec. "Standard dealiasing with truncation", Figs. 1, 5 and 7):
  * SPHERE keeps |k| < C_t N/2, i.e. |k|^2 <= K2max (the largest integer below
  * (C_t N/2)^2); CUBE keeps every |k_i| < C_t N/2; NO_MULTIPLE_ALIASES keeps the
  * modes of the sphere with |k_i| + |k_j| < 2N/3 for every pair of axes, so that
  * no double (or triple) alias of a state held in it reaches a kept mode
- * (identical to SPHERE for C_t <= 2 sqrt(2)/3; Fig. 7b at C_t = 1). */
-typedef enum { NS_MASK_SPHERE = 0, NS_MASK_CUBE = 1, NS_MASK_NO_MULTIPLE_ALIASES = 2 } ns_mask;
+ * (identical to SPHERE for C_t <= 2 sqrt(2)/3; Fig. 7b at C_t = 1); ROGALLO
+ * applies the same pair rule to the cube: Rogallo's truncation, the cube less
+ * thin prisms along its edges (Fig. 5). */
+typedef enum {
+  NS_MASK_SPHERE = 0,
+  NS_MASK_CUBE = 1,
+  NS_MASK_NO_MULTIPLE_ALIASES = 2,
+  NS_MASK_ROGALLO = 3
+} ns_mask;
 
-/* Phase-shift RK2 variants (Sec. "Extension to the multidimensional case"). */
+/* Step variants of ns_step_rk2_phaseshift.  The phase-shift RK2 schemes of Sec.
+ * "Extension to the multidimensional case" (0-2), the schemes without shifts they
+ * are compared against (Sec. "Time advancement", Euler and midpoint RK2: 3, 4),
+ * the Euler phase-shift scheme (Eq. sum_ps_non_ps in 3D: 5), and the fully exact
+ * scheme averaging every evaluation over the eight shifts in {0, 1/2}^3, which
+ * removes every alias class for any truncation (6; eight evaluations per stage). */
 typedef enum {
   NS_PS_EXACT = 0,  /* midpoint RK2, every evaluation the average over shifts 0 and (1/2,1/2,1/2) */
   NS_PS_APPROX = 1, /* Heun/Rogallo with alpha = 0, beta = (1/2,1/2,1/2) */
-  NS_PS_RANDOM = 2  /* Heun/Rogallo with alpha ~ U[0,1)^3 per step, beta = alpha + 1/2 (mod 1) */
+  NS_PS_RANDOM = 2, /* Heun/Rogallo with alpha ~ U[0,1)^3 per step, beta = alpha + 1/2 (mod 1) */
+  NS_RK2 = 3,       /* midpoint RK2 without shifts (truncation only) */
+  NS_EULER = 4,     /* forward Euler in integrating-factor form, without shifts */
+  NS_EULER_PS = 5,  /* Euler with the average over shifts 0 and (1/2,1/2,1/2) */
+  NS_PS_EXACT8 = 6  /* midpoint RK2, every evaluation the average over the 8 shifts {0,1/2}^3 */
 } ns_ps_variant;
 
 typedef struct {
@@ -130,7 +146,8 @@ size_t ns_workspace_bytes(const ns_config* cfg);
 /* Number of shells of the spectra for grid size n. */
 int32_t ns_num_shells(int32_t n);
 
-/* Largest retained |k|^2 (sphere) or |k_i| (cube) for cfg, -1 if cfg is invalid. */
+/* Largest retained |k|^2 (SPHERE, NO_MULTIPLE_ALIASES: of the sphere) or |k_i|
+ * (CUBE, ROGALLO: of the cube) for cfg, -1 if cfg is invalid. */
 int64_t ns_retained_bound(const ns_config* cfg);
 
 /* Create a context on `workspace` (device memory, >= ns_workspace_bytes(cfg)
@@ -161,8 +178,9 @@ ns_status ns_nonlinear(ns_ctx* ctx, const void* u_hat, void* n_hat, const double
 ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps);
 
 /* nsteps steps of phase-shift RK2 (Eqs. Rogallo1981 and its 3D form; split
- * forcing of Eq. forcing-eq when forcing != NULL, Heun variants only), in
- * place on u_hat.  variant: ns_ps_variant.  alphas: host array [nsteps][3] of
+ * forcing of Eq. forcing-eq when forcing != NULL, Heun variants only), or of
+ * one of the other ns_ps_variant schemes, in place on u_hat.  variant:
+ * an ns_ps_variant value, NS_ERR_ARG outside 0..6.  alphas: host array [nsteps][3] of
  * first-stage shifts for NS_PS_RANDOM, or NULL to draw them as
  * alpha_i = SplitMix64 uniform (cfg.seed, step0 + s, i); ignored by the other
  * variants.  step0 keys the random draws (shifts and forcing) of the first step,
@@ -171,6 +189,8 @@ ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps)
  *           A = 1/2 [N(.;0) + N(.;1/2)]
  *   heun:   S1 = E_dt(S0 + dt (N(S0;alpha) + O)),
  *           S = E_dt S0 + dt/2 E_{dt/2} (N(S0;alpha) + N(S1;beta) + 2 O)
+ *   rk2:    the exact formula with A = N(.;0); exact8: with A the 8-shift average
+ *   euler:  S = E_dt (S0 + dt A(S0)), A = N(.;0) or (euler_ps) the two-shift average
  * with E_tau = exp(-nu |k|^2 tau). */
 ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps,
                                  int32_t variant, const double* alphas,

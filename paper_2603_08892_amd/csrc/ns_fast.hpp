@@ -54,15 +54,12 @@ struct LineTest {
 };
 __device__ __forceinline__ LineTest line_test(const Geom& g, int ky, int kz) {
   LineTest L{0, g.n};
-  if (g.mask == 1) {
-    L.hi2 = (abs(ky) <= g.kmax && kz <= g.kmax) ? g.kmax * g.kmax : -1;
-  } else {
-    L.hi2 = (int)g.k2max - ky * ky - kz * kz;
-    if (g.mask == 2) {
-      // 3 (|k_x| + |k_y|) < 2N, 3 (|k_x| + |k_z|) < 2N and 3 (|k_y| + |k_z|) < 2N
-      const int b = abs(ky), c = abs(kz), n2 = 2 * g.n;
-      L.xmax = (3 * (b + c) < n2) ? (n2 - 1) / 3 - max(b, c) : -1;
-    }
+  if (cube_family(g)) L.hi2 = (abs(ky) <= g.kmax && kz <= g.kmax) ? g.kmax * g.kmax : -1;
+  else L.hi2 = (int)g.k2max - ky * ky - kz * kz;
+  if (g.mask >= 2) {
+    // 3 (|k_x| + |k_y|) < 2N, 3 (|k_x| + |k_z|) < 2N and 3 (|k_y| + |k_z|) < 2N
+    const int b = abs(ky), c = abs(kz), n2 = 2 * g.n;
+    L.xmax = (3 * (b + c) < n2) ? (n2 - 1) / 3 - max(b, c) : -1;
   }
   return L;
 }
@@ -344,9 +341,11 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   // all points for one-operand stages, half of them for two-operand ones; the first
   // chunk is read before the last transform so that its latency overlaps it
   constexpr bool need0 = (OP == OP_HEUN1 || OP == OP_EX1B || OP == OP_EX2B || OP == OP_RK4_0 ||
-                          OP == OP_RK4_1 || OP == OP_RK4_2);
+                          OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_MID1 || OP == OP_MID2 ||
+                          OP == OP_EUL || OP == OP_EULAV);
   constexpr bool need1 = (OP == OP_AVG || OP == OP_HEUN2 || OP == OP_EX1B || OP == OP_EX2B ||
-                          OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3);
+                          OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3 || OP == OP_ACC ||
+                          OP == OP_EULAV);
   constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
   constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
   const LineTest keep = line_test(g, ky, kz);
@@ -431,7 +430,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       Fv[2] = Fv[2] - scale(kd, kzr);
     }
     float eh = 1.f, edt = 1.f;
-    if (OP >= OP_HEUN1) { eh = a.eh[k2]; edt = a.edt[k2]; }
+    if (op_uses_etab(OP)) { eh = a.eh[k2]; edt = a.edt[k2]; }
     const float dt = a.dt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -453,9 +452,9 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       } else if (OP == OP_HEUN2) {
         st_off(out0, io0, s1 + scale(Nv, 0.5f * dt * eh));
       } else if (OP == OP_EX1B) {
-        st_off(out0, io0, scale(s0 + scale(s1 + Nv, 0.25f * dt), eh));
+        st_off(out0, io0, scale(s0 + scale(s1 + Nv, 0.5f * dt * a.w), eh));
       } else if (OP == OP_EX2B) {
-        st_off(out0, io0, scale(s0, edt) + scale(s1 + Nv, 0.5f * dt * eh));
+        st_off(out0, io0, scale(s0, edt) + scale(s1 + Nv, dt * a.w * eh));
       } else if (OP == OP_RK4_0) {
         st_off(out1, io1, scale(s0 + scale(Nv, 0.5f * dt), eh));
         st_off(out0, io0, scale(s0 + scale(Nv, dt / 6.f), edt));
@@ -465,8 +464,18 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       } else if (OP == OP_RK4_2) {
         st_off(out1, io1, scale(s0, edt) + scale(Nv, dt * eh));
         st_off(out0, io0, s1 + scale(Nv, dt / 3.f * eh));
-      } else {
+      } else if (OP == OP_RK4_3) {
         st_off(out0, io0, s1 + scale(Nv, dt / 6.f));
+      } else if (OP == OP_ACC) {
+        st_off(out0, io0, s1 + Nv);
+      } else if (OP == OP_MID1) {
+        st_off(out0, io0, scale(s0 + scale(Nv, 0.5f * dt), eh));
+      } else if (OP == OP_MID2) {
+        st_off(out0, io0, scale(s0, edt) + scale(Nv, dt * eh));
+      } else if (OP == OP_EUL) {
+        st_off(out0, io0, scale(s0 + scale(Nv, dt), edt));
+      } else {  // OP_EULAV
+        st_off(out0, io0, scale(s0 + scale(s1 + Nv, dt * a.w), edt));
       }
     }
   }

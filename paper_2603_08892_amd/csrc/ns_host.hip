@@ -79,10 +79,15 @@ struct Layout {
   size_t total;
 };
 
+bool cube_family_host(int mask) { return mask == NS_MASK_CUBE || mask == NS_MASK_ROGALLO; }
+
 bool retained_host(const Geom& g, long long kx, long long ky, long long kz) {
-  if (g.mask == 1) return std::llabs(kx) <= g.kmax && std::llabs(ky) <= g.kmax && kz <= g.kmax;
-  if (kx * kx + ky * ky + kz * kz > g.k2max) return false;
-  if (g.mask == 0) return true;
+  if (cube_family_host(g.mask)) {
+    if (std::llabs(kx) > g.kmax || std::llabs(ky) > g.kmax || kz > g.kmax) return false;
+  } else if (kx * kx + ky * ky + kz * kz > g.k2max) {
+    return false;
+  }
+  if (g.mask < 2) return true;
   const long long a = std::llabs(kx), b = std::llabs(ky), c = std::llabs(kz), n2 = 2LL * g.n;
   return 3 * (a + b) < n2 && 3 * (a + c) < n2 && 3 * (b + c) < n2;
 }
@@ -98,7 +103,7 @@ int isqrt_host(long long v) {
 }
 
 int ybound_host(const Geom& g, int kz) {
-  if (g.mask != 1) return isqrt_host(g.k2max - (long long)kz * kz);
+  if (!cube_family_host(g.mask)) return isqrt_host(g.k2max - (long long)kz * kz);
   return kz <= g.kmax ? g.kmax : -1;
 }
 
@@ -113,13 +118,13 @@ const char* validate(const ns_config* c) {
   if (c == nullptr) return "config is NULL";
   if (!factor_ok(c->n, nullptr)) return "n must be 2^a 3^b 5^c with a >= 1 and 8 <= n <= 1024";
   if (c->precision != NS_FP32 && c->precision != NS_FP64) return "precision must be NS_FP32 or NS_FP64";
-  if (c->mask != NS_MASK_SPHERE && c->mask != NS_MASK_CUBE && c->mask != NS_MASK_NO_MULTIPLE_ALIASES)
-    return "mask must be NS_MASK_SPHERE, NS_MASK_CUBE or NS_MASK_NO_MULTIPLE_ALIASES";
+  if (c->mask < NS_MASK_SPHERE || c->mask > NS_MASK_ROGALLO)
+    return "mask must be NS_MASK_SPHERE, NS_MASK_CUBE, NS_MASK_NO_MULTIPLE_ALIASES or NS_MASK_ROGALLO";
   if (c->flags & ~NS_CFG_GENERIC_PASSES) return "unknown config flags";
   if (!(c->nu >= 0.0) || !std::isfinite(c->nu)) return "nu must be finite and >= 0";
   if (!(c->ct > 0.0 && c->ct <= 1.0)) return "ct must satisfy 0 < ct <= 1";
   const double kmax = c->ct * c->n / 2.0;
-  if (c->mask != NS_MASK_CUBE ? largest_int_below(kmax * kmax) < 1 : largest_int_below(kmax) < 1)
+  if (!cube_family_host(c->mask) ? largest_int_below(kmax * kmax) < 1 : largest_int_below(kmax) < 1)
     return "ct too small: no non-zero mode is retained";
   return nullptr;
 }
@@ -133,7 +138,7 @@ bool make_layout(const ns_config* c, Layout* lay) {
   g.h = n / 2 + 1;
   g.mask = c->mask;
   const double kmax = c->ct * n / 2.0;
-  if (c->mask != NS_MASK_CUBE) {
+  if (!cube_family_host(c->mask)) {
     g.k2max = largest_int_below(kmax * kmax);
     g.kmax = isqrt_host(g.k2max);
     lay->k2top = g.k2max;
@@ -439,6 +444,7 @@ EpiArgs<R> epi(ns_ctx* c, int full) {
   a.eh = p.eh;
   a.edt = p.edt;
   a.full = full;
+  a.w = R(0.5);
   a.ntzf = c->lay.ntzf;
   a.lo0 = a.lo1 = a.li0 = a.li1 = compact_lay(c->lay);
   return a;
@@ -525,6 +531,73 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
   if (st != NS_OK) return st;
   const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
   for (int i = 0; i < nsteps; ++i) {
+    if (variant == NS_RK2) {
+      // midpoint RK2 without shifts: S_h = E_h (S0 + dt/2 N(S0)); S = E_dt S0 + dt E_h N(S_h)
+      EpiArgs<R> a = epi<R>(c, 0);
+      a.dt = R(dt);
+      a.in0 = s0;
+      a.li0 = U;
+      a.out0 = p.sb;
+      if ((st = eval<R, ns::OP_MID1>(c, s0, U, zero, a)) != NS_OK) return st;
+      EpiArgs<R> f = epi<R>(c, 1);
+      f.dt = R(dt);
+      f.in0 = s0;
+      f.li0 = U;
+      f.out0 = s0;
+      f.lo0 = U;
+      if ((st = eval<R, ns::OP_MID2>(c, p.sb, K, zero, f)) != NS_OK) return st;
+      continue;
+    }
+    if (variant == NS_EULER || variant == NS_EULER_PS) {
+      // S = E_dt (S0 + dt N_a) with N_a = N(S0) or the two-shift average
+      EpiArgs<R> f = epi<R>(c, 1);
+      f.dt = R(dt);
+      f.in0 = s0;
+      f.li0 = U;
+      f.out0 = s0;
+      f.lo0 = U;
+      if (variant == NS_EULER) {
+        if ((st = eval<R, ns::OP_EUL>(c, s0, U, zero, f)) != NS_OK) return st;
+        continue;
+      }
+      EpiArgs<R> a = epi<R>(c, 0);
+      a.out0 = p.ab;
+      if ((st = eval<R, ns::OP_STORE>(c, s0, U, zero, a)) != NS_OK) return st;
+      f.in1 = p.ab;
+      if ((st = eval<R, ns::OP_EULAV>(c, s0, U, half, f)) != NS_OK) return st;
+      continue;
+    }
+    if (variant == NS_PS_EXACT8) {
+      // midpoint RK2, every evaluation averaged over the eight shifts in {0, 1/2}^3:
+      // the first seven are summed into ab, the eighth closes the stage with w = 1/8
+      const double s8[8][3] = {{0, 0, 0},     {0, 0, 0.5},   {0, 0.5, 0},   {0, 0.5, 0.5},
+                               {0.5, 0, 0},   {0.5, 0, 0.5}, {0.5, 0.5, 0}, {0.5, 0.5, 0.5}};
+      for (int stage = 0; stage < 2; ++stage) {
+        const Cx<R>* x = stage == 0 ? s0 : p.sb;
+        const ns::Lay lx = stage == 0 ? U : K;
+        EpiArgs<R> a = epi<R>(c, 0);
+        a.out0 = p.ab;
+        if ((st = eval<R, ns::OP_STORE>(c, x, lx, s8[0], a)) != NS_OK) return st;
+        a.in1 = p.ab;
+        for (int j = 1; j < 7; ++j)
+          if ((st = eval<R, ns::OP_ACC>(c, x, lx, s8[j], a)) != NS_OK) return st;
+        EpiArgs<R> f = epi<R>(c, stage);
+        f.dt = R(dt);
+        f.w = R(0.125);
+        f.in0 = s0;
+        f.li0 = U;
+        f.in1 = p.ab;
+        if (stage == 0) {
+          f.out0 = p.sb;
+          if ((st = eval<R, ns::OP_EX1B>(c, x, lx, s8[7], f)) != NS_OK) return st;
+        } else {
+          f.out0 = s0;
+          f.lo0 = U;
+          if ((st = eval<R, ns::OP_EX2B>(c, x, lx, s8[7], f)) != NS_OK) return st;
+        }
+      }
+      continue;
+    }
     if (variant == NS_PS_EXACT) {
       EpiArgs<R> a = epi<R>(c, 0);
       a.dt = R(dt);
@@ -753,7 +826,7 @@ int64_t ns_retained_bound(const ns_config* cfg) {
   if (m) { g_last_error = m; return -1; }
   Layout lay;
   make_layout(cfg, &lay);
-  return cfg->mask != NS_MASK_CUBE ? lay.g.k2max : lay.g.kmax;
+  return !cube_family_host(cfg->mask) ? lay.g.k2max : lay.g.kmax;
 }
 
 ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx** out) {
@@ -846,10 +919,10 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
   if (!aligned(u_hat)) return fail(ctx, NS_ERR_ARG, "u_hat must be a non-NULL 256-byte aligned device pointer");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(ctx, NS_ERR_ARG, "nsteps must be >= 0");
-  if (variant != NS_PS_EXACT && variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
-    return fail(ctx, NS_ERR_ARG, "unknown phase-shift variant");
+  if (variant < NS_PS_EXACT || variant > NS_PS_EXACT8) return fail(ctx, NS_ERR_ARG, "unknown scheme variant");
   if (forcing) {
-    if (variant == NS_PS_EXACT) return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
+    if (variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
+      return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
     if (forcing->k2_lo != 4 || forcing->k2_hi != 9) return fail(ctx, NS_ERR_ARG, "forcing shell must be 4 <= |k|^2 <= 9");
     if (!(forcing->injection > 0.0) || !std::isfinite(forcing->injection)) return fail(ctx, NS_ERR_ARG, "injection must be finite and > 0");
     const Geom& g = ctx->lay.g;
@@ -913,7 +986,7 @@ ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, doub
   if (u_hat0 == lam) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must not overlap");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
   if (variant != NS_PS_EXACT && variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
-    return fail(ctx, NS_ERR_ARG, "unknown phase-shift variant");
+    return fail(ctx, NS_ERR_ARG, "the adjoint supports NS_PS_EXACT, NS_PS_APPROX and NS_PS_RANDOM only");
   if (variant == NS_PS_RANDOM && (alpha == nullptr || !std::isfinite(alpha[0]) || !std::isfinite(alpha[1]) ||
                                   !std::isfinite(alpha[2])))
     return fail(ctx, NS_ERR_ARG, "NS_PS_RANDOM needs the finite first-stage shift alpha");

@@ -26,7 +26,7 @@ struct Geom {
   int kzp;          // k_z stride of the scratch fields (kzn rounded up)
   int L;            // k_z columns per strided tile (power of two)
   int lgL;          // log2(L)
-  int mask;         // 0 sphere, 1 cube, 2 sphere without the double-alias reach
+  int mask;         // 0 sphere, 1 cube, 2 sphere / 3 cube without the double-alias reach
   int kmax;         // largest retained |k_i|
   long long k2max;  // sphere: largest retained |k|^2; cube: 3 kmax^2
   long long comp;   // state component stride, n*n*h
@@ -43,10 +43,15 @@ __device__ __forceinline__ bool double_alias_free(const Geom& g, int kx, int ky,
   return 3 * (a + b) < n2 && 3 * (a + c) < n2 && 3 * (b + c) < n2;
 }
 
+__device__ __forceinline__ bool cube_family(const Geom& g) { return g.mask == 1 || g.mask == 3; }
+
 __device__ __forceinline__ bool retained(const Geom& g, int kx, int ky, int kz) {
-  if (g.mask == 1) return abs(kx) <= g.kmax && abs(ky) <= g.kmax && kz <= g.kmax;
-  if ((long long)kx * kx + (long long)ky * ky + (long long)kz * kz > g.k2max) return false;
-  return g.mask == 0 || double_alias_free(g, kx, ky, kz);
+  if (cube_family(g)) {
+    if (abs(kx) > g.kmax || abs(ky) > g.kmax || kz > g.kmax) return false;
+  } else if ((long long)kx * kx + (long long)ky * ky + (long long)kz * kz > g.k2max) {
+    return false;
+  }
+  return g.mask < 2 || double_alias_free(g, kx, ky, kz);
 }
 
 __device__ __forceinline__ int isqrt_ll(long long v) {
@@ -57,10 +62,10 @@ __device__ __forceinline__ int isqrt_ll(long long v) {
   return r;
 }
 
-// Largest |k_y| that can be retained on k_z plane kz (-1: none); for the
-// no-multiple-aliases mask the sphere's bound (a superset).
+// Largest |k_y| that can be retained on k_z plane kz (-1: none); for the masks
+// without the double-alias reach the bound of their sphere or cube (a superset).
 __device__ __forceinline__ int ybound(const Geom& g, int kz) {
-  if (g.mask != 1) return isqrt_ll(g.k2max - (long long)kz * kz);
+  if (!cube_family(g)) return isqrt_ll(g.k2max - (long long)kz * kz);
   return kz <= g.kmax ? g.kmax : -1;
 }
 
@@ -319,13 +324,25 @@ enum EpiOp {
   OP_AVG = 1,    // out0 = (in1 + N)/2
   OP_HEUN1 = 2,  // out1 = E_dt (S0 + dt (N + O)); out0 = E_dt S0 + dt/2 E_h (N + 2 O)
   OP_HEUN2 = 3,  // out0 = in1 + dt/2 E_h N
-  OP_EX1B = 4,   // out0 = E_h (S0 + dt/2 (in1 + N)/2)
-  OP_EX2B = 5,   // out0 = E_dt S0 + dt E_h (in1 + N)/2
+  OP_EX1B = 4,   // out0 = E_h (S0 + dt/2 w (in1 + N))
+  OP_EX2B = 5,   // out0 = E_dt S0 + dt E_h w (in1 + N)
   OP_RK4_0 = 6,  // out1 = E_h (S0 + dt/2 N); out0 = E_dt S0 + dt/6 E_dt N
   OP_RK4_1 = 7,  // out1 = E_h S0 + dt/2 N;   out0 = in1 + dt/3 E_h N
   OP_RK4_2 = 8,  // out1 = E_dt S0 + dt E_h N; out0 = in1 + dt/3 E_h N
-  OP_RK4_3 = 9   // out0 = in1 + dt/6 N
+  OP_RK4_3 = 9,  // out0 = in1 + dt/6 N
+  OP_ACC = 10,   // out0 = in1 + N
+  OP_MID1 = 11,  // out0 = E_h (S0 + dt/2 N)
+  OP_MID2 = 12,  // out0 = E_dt S0 + dt E_h N
+  OP_EUL = 13,   // out0 = E_dt (S0 + dt N)
+  OP_EULAV = 14  // out0 = E_dt (S0 + dt w (in1 + N))
 };
+// w (EpiArgs::w) weighs each of the shifted evaluations summed in in1 + N: 1/2 for
+// the two-shift average, 1/8 for the average over the eight shifts in {0, 1/2}^3.
+
+// Ops whose stage formula uses the integrating factors E_h and E_dt.
+__host__ __device__ constexpr bool op_uses_etab(int op) {
+  return op != OP_STORE && op != OP_AVG && op != OP_ACC;
+}
 
 template <typename R>
 struct EpiArgs {
@@ -338,6 +355,7 @@ struct EpiArgs {
   const R* edt;       // exp(-nu k^2 dt)
   const Cx<R>* force; // [3][7][7][4] forcing on |k_i| <= 3, or null
   R dt;
+  R w;                // weight of each summed evaluation (OP_EX1B, OP_EX2B, OP_EULAV)
   int full;           // 1: blocks cover every (k_y, k_z tile) of the half spectrum and write zeros outside
   int ntzf;           // k_z tiles over [0, N/2] in full mode
 };
@@ -431,7 +449,7 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
       F[2] = F[2] - scale(kd, kzr);
     }
     R eh = R(1), edt = R(1);
-    if (OP >= OP_HEUN1) { eh = a.eh[k2]; edt = a.edt[k2]; }
+    if (op_uses_etab(OP)) { eh = a.eh[k2]; edt = a.edt[k2]; }
     const R dt = a.dt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -453,10 +471,10 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
         a.out0[o0] = a.in1[i1] + scale(N, R(0.5) * dt * eh);
       } else if (OP == OP_EX1B) {
         const Cx<R> s0 = a.in0[i0];
-        a.out0[o0] = scale(s0 + scale(a.in1[i1] + N, R(0.25) * dt), eh);
+        a.out0[o0] = scale(s0 + scale(a.in1[i1] + N, R(0.5) * dt * a.w), eh);
       } else if (OP == OP_EX2B) {
         const Cx<R> s0 = a.in0[i0];
-        a.out0[o0] = scale(s0, edt) + scale(a.in1[i1] + N, R(0.5) * dt * eh);
+        a.out0[o0] = scale(s0, edt) + scale(a.in1[i1] + N, dt * a.w * eh);
       } else if (OP == OP_RK4_0) {
         const Cx<R> s0 = a.in0[i0];
         a.out1[o1] = scale(s0 + scale(N, R(0.5) * dt), eh);
@@ -469,8 +487,18 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
         const Cx<R> s0 = a.in0[i0];
         a.out1[o1] = scale(s0, edt) + scale(N, dt * eh);
         a.out0[o0] = a.in1[i1] + scale(N, dt / R(3) * eh);
-      } else {  // OP_RK4_3
+      } else if (OP == OP_RK4_3) {
         a.out0[o0] = a.in1[i1] + scale(N, dt / R(6));
+      } else if (OP == OP_ACC) {
+        a.out0[o0] = a.in1[i1] + N;
+      } else if (OP == OP_MID1) {
+        a.out0[o0] = scale(a.in0[i0] + scale(N, R(0.5) * dt), eh);
+      } else if (OP == OP_MID2) {
+        a.out0[o0] = scale(a.in0[i0], edt) + scale(N, dt * eh);
+      } else if (OP == OP_EUL) {
+        a.out0[o0] = scale(a.in0[i0] + scale(N, dt), edt);
+      } else {  // OP_EULAV
+        a.out0[o0] = scale(a.in0[i0] + scale(a.in1[i1] + N, dt * a.w), edt);
       }
     }
   }

@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(PKG, "libns.so")
 
 NS_OK, NS_ERR_ARG, NS_ERR_SIZE, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(6)
 NS_FP32, NS_FP64 = 0, 1
-NS_MASK_SPHERE, NS_MASK_CUBE, NS_MASK_NO_MULTIPLE_ALIASES = 0, 1, 2
-MASKS = {"sphere": NS_MASK_SPHERE, "cube": NS_MASK_CUBE, "no_multiple_aliases": NS_MASK_NO_MULTIPLE_ALIASES}
-NS_PS_EXACT, NS_PS_APPROX, NS_PS_RANDOM = 0, 1, 2
+NS_MASK_SPHERE, NS_MASK_CUBE, NS_MASK_NO_MULTIPLE_ALIASES, NS_MASK_ROGALLO = 0, 1, 2, 3
+MASKS = {"sphere": NS_MASK_SPHERE, "cube": NS_MASK_CUBE, "no_multiple_aliases": NS_MASK_NO_MULTIPLE_ALIASES,
+         "rogallo": NS_MASK_ROGALLO}
+NS_PS_EXACT, NS_PS_APPROX, NS_PS_RANDOM, NS_RK2, NS_EULER, NS_EULER_PS, NS_PS_EXACT8 = range(7)
 NS_NL_PS_AVG = 1
-VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM}
+VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM, "rk2": NS_RK2,
+            "euler": NS_EULER, "euler_ps": NS_EULER_PS, "exact8": NS_PS_EXACT8}
 
 # every function declared in include/ns.h
 ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns_init", "ns_destroy",
@@ -188,8 +190,11 @@ class Solver:
         return u
 
     def step_ps(self, u, dt, nsteps=1, variant="random", alphas=None, forcing=None, step0=0):
-        """Phase-shift RK2 steps in place.  alphas: array [nsteps, 3] (random variant) or None;
-        forcing: dict(seed=..., injection=1.0) or None."""
+        """Steps in place of one of VARIANTS: the phase-shift RK2 schemes ("exact", "approx",
+        "random"), midpoint RK2 and Euler without shifts ("rk2", "euler"), Euler with the
+        two-shift average ("euler_ps") and the eight-shift exact RK2 ("exact8").
+        alphas: array [nsteps, 3] (random variant) or None; forcing: dict(seed=...,
+        injection=1.0) or None (Heun variants only)."""
         self._sync_stream()
         ap = None
         if alphas is not None:

@@ -45,14 +45,16 @@ def test_retained_bounds_match_oracle(n, ct):
 
 @pytest.mark.parametrize("n", [8, 12, 16, 32, 128, 192, 360])
 @pytest.mark.parametrize("ct", [2 / 3, 0.97, 1.0])
-def test_no_multiple_aliases_bound_is_the_sphere(n, ct):
+def test_pair_rule_masks_bound_by_their_sphere_or_cube(n, ct):
     assert ns.retained_bound(n, ct, "no_multiple_aliases") == grid.sphere_k2max(n, ct)
+    assert ns.retained_bound(n, ct, "rogallo") == grid.cube_kmax(n, ct)
 
 
-def test_unknown_mask_rejected():
+@pytest.mark.parametrize("bad", [-1, 4])
+def test_unknown_mask_rejected(bad):
     L = ns.lib()
     cfg = ns.make_config(32, 0.1, 1.0)
-    cfg.mask = 3
+    cfg.mask = bad
     assert L.ns_workspace_bytes(ctypes.byref(cfg)) == 0
     assert b"mask" in L.ns_last_error(None)
 

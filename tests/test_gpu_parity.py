@@ -47,7 +47,7 @@ def _check(got, want, prec, what=""):
 
 
 def _field(n, ct, mask, seed, energy=None):
-    k2 = 3 * grid.cube_kmax(n, ct) ** 2 if mask == "cube" else grid.sphere_k2max(n, ct)
+    k2 = 3 * grid.cube_kmax(n, ct) ** 2 if mask in ("cube", "rogallo") else grid.sphere_k2max(n, ct)
     u = inputs.random_solenoidal(n, seed, k2, energy=energy)
     return u * grid.mask(n, ct, mask)
 
@@ -60,6 +60,8 @@ NL_CASES = [
     (128, 2 / 3, "cube", "fp32"), (192, 2 / 3, "sphere", "fp32"), (256, 1.0, "sphere", "fp32"),
     (16, 1.0, "no_multiple_aliases", "fp64"), (24, 0.97, "no_multiple_aliases", "fp64"),
     (64, 1.0, "no_multiple_aliases", "fp32"), (128, 1.0, "no_multiple_aliases", "fp32"),
+    (24, 1.0, "rogallo", "fp64"), (30, 0.9, "rogallo", "fp64"), (64, 1.0, "rogallo", "fp32"),
+    (128, 1.0, "rogallo", "fp32"), (192, 1.0, "rogallo", "fp32"),
 ]
 
 
@@ -89,14 +91,15 @@ def test_nonlinear_ignores_modes_outside_mask():
     assert np.all(got[:, ~m] == 0)
 
 
-@pytest.mark.parametrize("n,ct", [(24, 1.0), (30, 0.98)])
-def test_no_multiple_aliases_pair_average_is_clean(n, ct):
-    """With the "no_multiple_aliases" truncation the GPU's isotropic pair average is the
-    alias-free (padded) product of the oracle, and the output is zero outside the mask
-    even for an input that fills every mode."""
-    s = _solver(n, ct, "no_multiple_aliases", "fp64")
-    m = grid.mask(n, ct, "no_multiple_aliases")
-    u = _field(n, ct, "no_multiple_aliases", 300 + n)
+@pytest.mark.parametrize("n,ct,mask", [(24, 1.0, "no_multiple_aliases"), (30, 0.98, "no_multiple_aliases"),
+                                       (24, 1.0, "rogallo"), (30, 0.9, "rogallo")])
+def test_pair_rule_masks_pair_average_is_clean(n, ct, mask):
+    """With the "no_multiple_aliases" and Rogallo truncations the GPU's isotropic pair
+    average is the alias-free (padded) product of the oracle, and the output is zero
+    outside the mask even for an input that fills every mode."""
+    s = _solver(n, ct, mask, "fp64")
+    m = grid.mask(n, ct, mask)
+    u = _field(n, ct, mask, 300 + n)
     _check(_host(s.nonlinear(s.to_device(u), ps_avg=True)), onl.nonlinear_pad(u, m), "fp64", "clean")
     full = inputs.random_solenoidal(n, 9, 3 * (n // 2) ** 2)
     got = _host(s.nonlinear(s.to_device(full)))
@@ -104,13 +107,14 @@ def test_no_multiple_aliases_pair_average_is_clean(n, ct):
     assert np.all(got[:, ~m] == 0)
 
 
+@pytest.mark.parametrize("mask", ["no_multiple_aliases", "rogallo"])
 @pytest.mark.parametrize("scheme", ["rk4", "exact", "random"])
-def test_no_multiple_aliases_step(scheme):
+def test_pair_rule_masks_step(scheme, mask):
     n, ct, nu, dt = 32, 1.0, 0.02, 0.01
-    s = _solver(n, ct, "no_multiple_aliases", "fp64", nu=nu, seed=12)
-    m = grid.mask(n, ct, "no_multiple_aliases")
+    s = _solver(n, ct, mask, "fp64", nu=nu, seed=12)
+    m = grid.mask(n, ct, mask)
     model = onl.NSModel(n, nu, m)
-    u = _field(n, ct, "no_multiple_aliases", 41, energy=0.5)
+    u = _field(n, ct, mask, 41, energy=0.5)
     ud = s.to_device(u)
     if scheme == "rk4":
         s.step_rk4(ud, dt, 1)
@@ -147,10 +151,10 @@ def test_taylor_green_closed_form_on_gpu():
 
 
 def _oracle_step(model, u, dt, scheme, alpha=None, force=None):
-    if scheme == "rk4":
-        return schemes.rk4(model, u, dt)
-    if scheme == "exact":
-        return schemes.ps_exact(model, u, dt)
+    plain = {"rk4": schemes.rk4, "exact": schemes.ps_exact, "rk2": schemes.rk2, "euler": schemes.euler,
+             "euler_ps": schemes.euler_ps, "exact8": schemes.ps_exact8}
+    if scheme in plain:
+        return plain[scheme](model, u, dt)
     return schemes.ps_heun(model, u, dt, alpha, forcing=force)
 
 
@@ -158,7 +162,7 @@ STEP_CASES = [(16, 1.0, "fp64"), (24, 2 / 3, "fp64"), (32, 1.0, "fp32"), (48, 0.
 
 
 @pytest.mark.parametrize("n,ct,prec", STEP_CASES)
-@pytest.mark.parametrize("scheme", ["rk4", "exact", "approx", "random"])
+@pytest.mark.parametrize("scheme", ["rk4", "exact", "approx", "random", "rk2", "euler", "euler_ps", "exact8"])
 def test_one_step_parity(n, ct, prec, scheme):
     print(f"[step] n={n} ct={ct:.4f} prec={prec} scheme={scheme}", flush=True)
     nu, dt = 0.02, 0.01
@@ -176,6 +180,9 @@ def test_one_step_parity(n, ct, prec, scheme):
     elif scheme == "approx":
         s.step_ps(ud, dt, 1, "approx")
         want = _oracle_step(model, u, dt, "heun", alpha=(0, 0, 0))
+    elif scheme != "random":
+        s.step_ps(ud, dt, 1, scheme)
+        want = _oracle_step(model, u, dt, scheme)
     else:
         s.step_ps(ud, dt, 1, "random", step0=5)            # alpha from SplitMix64(seed, 5)
         want = _oracle_step(model, u, dt, "heun", alpha=oforcing.random_shift(77, 5))
@@ -287,6 +294,15 @@ def test_zero_steps_and_argument_errors():
         s.step_rk4(ud, -0.1, 1)
     with pytest.raises(ns.NSError):
         s.step_ps(ud, 0.1, 1, "exact", forcing={"seed": 1})
+    lam = s.to_device(u)
+    for v in ("rk2", "euler", "euler_ps", "exact8"):    # forcing and the adjoint: Heun/PS variants only
+        with pytest.raises(ns.NSError):
+            s.step_ps(ud, 0.1, 1, v, forcing={"seed": 1})
+        with pytest.raises(ns.NSError):
+            s.vjp_ps(ud, lam, 0.1, v)
+    for bad in (-1, 7):
+        assert ns.lib().ns_step_rk2_phaseshift(s.ctx, s._field(ud, "u"), 0.1, 1, bad, None, None, 0) == ns.NS_ERR_ARG
+    assert np.array_equal(_host(ud), u)
     with pytest.raises(ns.NSError):
         s.nonlinear(ud, out=ud)
 
@@ -305,7 +321,8 @@ def test_energy_conservation_on_gpu():
 
 @pytest.mark.parametrize("n,ct,mask", [(64, 1.0, "sphere"), (128, 1.0, "sphere"), (128, 2 / 3, "sphere"),
                                        (192, 2 / 3, "sphere"), (256, 1.0, "sphere"),
-                                       (128, 1.0, "no_multiple_aliases"), (128, 2 / 3, "cube")])
+                                       (128, 1.0, "no_multiple_aliases"), (128, 2 / 3, "cube"),
+                                       (192, 1.0, "rogallo")])
 def test_specialised_passes_match_generic(n, ct, mask):
     """The compile-time FP32 passes (N = 64, 128, 192, 256) and the size-generic passes
     agree to FP32 round-off (each is within ~5e-6 of the FP64 oracle), for the
@@ -319,7 +336,7 @@ def test_specialised_passes_match_generic(n, ct, mask):
         a = _host(fast.nonlinear(fast.to_device(u), shift=shift))
         b = _host(gen.nonlinear(gen.to_device(u), shift=shift))
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5, shift
-    for scheme in ("rk4", "exact", "approx", "random"):
+    for scheme in ("rk4", "exact", "approx", "random", "rk2", "euler", "euler_ps", "exact8"):
         ua, ub = fast.to_device(u), gen.to_device(u)
         for s_, ud in ((fast, ua), (gen, ub)):
             if scheme == "rk4":
