@@ -224,6 +224,40 @@ ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, doub
 ns_status ns_timing_enable(ns_ctx* ctx, int32_t enable);
 ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches);
 
+/* ---- The 1D model dS/dt = -S^2 (Sec. "Phase shifting for one-dimensional
+ * problems", Eqs. model-1d-2 and 1d_initial; the scheme comparison of Fig. 8).
+ * A batch of independent real signals of n points on [0, 2 pi), each held as its
+ * spectrum s_hat[b][k], k = 0..n/2 (FP64 complex, interleaved re/im, rows of
+ * n/2 + 1 entries; forward transform normalised by 1/n, inverse unnormalised).
+ * Truncation keeps k < ct n/2 (the strict reading of the 3D masks), in and out;
+ * there is no viscosity, so no integrating factor.  N(S; s) is the product
+ * evaluated on the grid shifted by s cells and shifted back:
+ *   N(S; s)_k = M_k conj(phi_k) FFT(-(IFFT(phi M S))^2)_k,  phi_k = exp(2 pi i k s / n).
+ * Device pointers, 16-byte aligned (may be NULL when batch is 0), owned by the
+ * caller; work is enqueued on
+ * `stream` (a hipStream_t, NULL for the default stream) and not waited for.
+ * Host checks (NS_ERR_ARG, message from ns_last_error(NULL)): n even with
+ * 4 <= n <= 1024, 0 < ct <= 1 with at least one mode k >= 1 kept, batch >= 0.
+ * Launch failures return NS_ERR_HIP. */
+typedef enum {
+  NS1D_EULER = 0,     /* S = S0 + dt N(S0; 0) */
+  NS1D_EULER_PS = 1,  /* S = S0 + dt A(S0), A = 1/2 [N(.; 0) + N(.; 1/2)] (Eq. sum_ps_non_ps) */
+  NS1D_RK2 = 2,       /* midpoint: S_h = S0 + dt/2 N(S0; 0), S = S0 + dt N(S_h; 0) */
+  NS1D_PS_EXACT = 3,  /* the midpoint formula with A in place of N at both stages */
+  NS1D_PS_APPROX = 4, /* Heun: S1 = S0 + dt N(S0; 0), S = S0 + dt/2 [N(S0; 0) + N(S1; 1/2)] (Eq. Rogallo1981) */
+  NS1D_RK4 = 5        /* classical four-stage Runge-Kutta, unshifted */
+} ns1d_scheme;
+
+/* n_hat[b] = N(s_hat[b]; shift) for every signal (n_hat may alias s_hat). */
+ns_status ns1d_nonlinear(const void* s_hat, void* n_hat, int32_t n, double ct, int32_t batch,
+                         double shift, void* stream);
+
+/* nsteps steps of an ns1d_scheme value on every signal, in place; one block per
+ * signal keeps all stages on chip.  Also NS_ERR_ARG for dt not finite and > 0,
+ * nsteps < 0 or an unknown scheme. */
+ns_status ns1d_step(void* s_hat, int32_t n, double ct, int32_t batch, double dt, int32_t nsteps,
+                    int32_t scheme, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@
 #include "ns_adjoint.hpp"
 #include "ns_fast.hpp"
 #include "ns_aux_kernels.hpp"
+#include "ns_model1d.hpp"
 
 using ns::Cx;
 using ns::EpiArgs;
@@ -941,6 +942,62 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
   return ctx->cfg.precision == NS_FP32
              ? ps_t<float>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0)
              : ps_t<double>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0);
+}
+
+namespace {
+
+// Host checks shared by the two entry points of the 1D model; the message is kept
+// as the thread's last error.
+ns_status check1d(int32_t n, double ct, int32_t batch, const void* a, const void* b, int* kmax) {
+  if (n < 4 || n > 1024 || (n % 2) != 0) return fail(nullptr, NS_ERR_ARG, "n must be even with 4 <= n <= 1024");
+  if (!(ct > 0.0 && ct <= 1.0)) return fail(nullptr, NS_ERR_ARG, "ct must satisfy 0 < ct <= 1");
+  const long long km = largest_int_below(ct * n / 2.0);
+  if (km < 1) return fail(nullptr, NS_ERR_ARG, "ct too small: no non-zero mode is retained");
+  if (batch < 0) return fail(nullptr, NS_ERR_ARG, "batch must be >= 0");
+  for (const void* p : {a, b})
+    if (batch > 0 && (p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16) != 0))
+      return fail(nullptr, NS_ERR_ARG, "spectra must be non-NULL 16-byte aligned device pointers");
+  *kmax = (int)km;
+  return NS_OK;
+}
+
+ns_status launch1d(const ns1d::Args& a, int32_t batch, void* stream) {
+  if (batch == 0) return NS_OK;
+  const size_t lds = ns1d::lds_bytes(a.n);
+  hipError_t e = allow_lds(ns1d::k_model1d, lds);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(ns1d::k_model1d, dim3((unsigned)batch), dim3(ns1d::kThreads), lds,
+                       static_cast<hipStream_t>(stream), a);
+    e = hipGetLastError();
+  }
+  return hip_check(nullptr, e, "1D model launch");
+}
+
+}  // namespace
+
+ns_status ns1d_nonlinear(const void* s_hat, void* n_hat, int32_t n, double ct, int32_t batch, double shift,
+                         void* stream) {
+  int kmax = 0;
+  ns_status st = check1d(n, ct, batch, s_hat, n_hat, &kmax);
+  if (st != NS_OK) return st;
+  if (!std::isfinite(shift)) return fail(nullptr, NS_ERR_ARG, "shift must be finite");
+  ns1d::Args a{static_cast<const double2*>(s_hat), static_cast<double2*>(n_hat), n, n / 2 + 1, kmax, 0.0, 0, -1,
+               shift};
+  return launch1d(a, batch, stream);
+}
+
+ns_status ns1d_step(void* s_hat, int32_t n, double ct, int32_t batch, double dt, int32_t nsteps, int32_t scheme,
+                    void* stream) {
+  int kmax = 0;
+  ns_status st = check1d(n, ct, batch, s_hat, s_hat, &kmax);
+  if (st != NS_OK) return st;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(nullptr, NS_ERR_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(nullptr, NS_ERR_ARG, "nsteps must be >= 0");
+  if (scheme < NS1D_EULER || scheme > NS1D_RK4) return fail(nullptr, NS_ERR_ARG, "unknown 1D scheme");
+  if (nsteps == 0) return NS_OK;
+  ns1d::Args a{static_cast<const double2*>(s_hat), static_cast<double2*>(s_hat), n, n / 2 + 1, kmax, dt, nsteps,
+               scheme, 0.0};
+  return launch1d(a, batch, stream);
 }
 
 ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out) {

@@ -117,3 +117,23 @@ def shear_wave(n, k=2):
 def random_shifts(seed, nsteps):
     """Shifts alpha ~ U[0,1)^3 per step, in grid-spacing units, shape [nsteps, 3]."""
     return np.random.default_rng(seed).random((nsteps, 3))
+
+
+def model1d_initial(n, k0=10, amp=0.7):
+    """Spectrum k = 0..n/2 of S0 = 1 + amp cos(k0 x) (the 1D model's initial value)."""
+    s = np.zeros(n // 2 + 1, dtype=np.complex128)
+    s[0] = 1.0
+    s[k0] = amp / 2.0
+    return s
+
+
+def model1d_random(n, seed, batch, kmax, amp=0.3):
+    """Batch of real signals 1 + (random modes 1..kmax with Gaussian coefficients,
+    amplitudes falling as exp(-(k/8)^2)), spectra [batch, n/2 + 1]."""
+    rng = np.random.default_rng(seed)
+    s = np.zeros((batch, n // 2 + 1), dtype=np.complex128)
+    k = np.arange(1, kmax + 1)
+    s[:, 0] = 1.0
+    s[:, 1:kmax + 1] = amp * np.exp(-(k / 8.0) ** 2) * (rng.standard_normal((batch, kmax))
+                                                        + 1j * rng.standard_normal((batch, kmax))) / np.sqrt(2)
+    return s

@@ -31,7 +31,7 @@ VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM
 ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns_init", "ns_destroy",
                  "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
                  "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift", "ns_timing_enable",
-                 "ns_timing_read")
+                 "ns_timing_read", "ns1d_nonlinear", "ns1d_step")
 PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue")
 
 
@@ -85,6 +85,8 @@ def lib():
         "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P]),
         "ns_timing_enable": (I32, [P, I32]),
         "ns_timing_read": (I32, [P, P, P]),
+        "ns1d_nonlinear": (I32, [P, P, I32, D, I32, D, P]),
+        "ns1d_step": (I32, [P, I32, D, I32, D, I32, I32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -241,3 +243,45 @@ class Solver:
         self._check(lib().ns_timing_read(self.ctx, ms.ctypes.data_as(ctypes.c_void_p),
                                          cnt.ctypes.data_as(ctypes.c_void_p)))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(PASS_NAMES)}
+
+
+# ---------------------------------------------------------------- the 1D model
+SCHEMES_1D = {"euler": 0, "euler_ps": 1, "rk2": 2, "ps_exact": 3, "ps_approx": 4, "rk4": 5}
+
+
+def _spectra_1d(s, n, name):
+    import torch
+    h = n // 2 + 1
+    if (s.dtype != torch.complex128 or s.dim() != 2 or s.shape[1] != h or not s.is_contiguous()
+            or s.device.type != "cuda"):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape [batch, {h}]")
+    return ctypes.c_void_p(s.data_ptr()), int(s.shape[0])
+
+
+def _check1d(st):
+    if st != NS_OK:
+        raise NSError(st, lib().ns_last_error(None).decode())
+
+
+def _stream1d(s):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(s.device).cuda_stream)
+
+
+def model1d_nonlinear(s, n, ct, shift=0.0, out=None):
+    """N(S; shift) of the 1D model dS/dt = -S^2 for a batch of spectra s [batch, n/2 + 1]."""
+    import torch
+    p, b = _spectra_1d(s, n, "s")
+    out = torch.empty_like(s) if out is None else out
+    q, bo = _spectra_1d(out, n, "out")
+    if bo != b:
+        raise ValueError("out must have the batch size of s")
+    _check1d(lib().ns1d_nonlinear(p, q, int(n), float(ct), b, float(shift), _stream1d(s)))
+    return out
+
+
+def model1d_step(s, n, ct, dt, nsteps=1, scheme="ps_exact"):
+    """nsteps steps of one of SCHEMES_1D on a batch of spectra s [batch, n/2 + 1], in place."""
+    p, b = _spectra_1d(s, n, "s")
+    _check1d(lib().ns1d_step(p, int(n), float(ct), b, float(dt), int(nsteps), SCHEMES_1D[scheme], _stream1d(s)))
+    return s

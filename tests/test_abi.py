@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     with open(os.path.join(ROOT, "include", "ns.h")) as f:
         text = f.read()
-    return sorted(set(re.findall(r"\b(ns_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ns(?:1d)?_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -118,3 +118,24 @@ def test_workspace_scales_with_grid():
     assert 6 < big / small < 10
     # the pruned scratch is smaller for 2/3 truncation than for C_t = 1
     assert ns.workspace_bytes(192, 0.01, 2 / 3) < ns.workspace_bytes(192, 0.01, 1.0)
+
+
+@pytest.mark.parametrize("n,ct,batch,ptr", [(7, 1.0, 1, 256), (2, 1.0, 1, 256), (2048, 1.0, 1, 256),
+                                            (8, 0.0, 1, 256), (8, 0.2, 1, 256), (16, 1.0, -1, 256),
+                                            (16, 1.0, 1, None), (16, 1.0, 1, 264)])
+def test_model1d_argument_errors(n, ct, batch, ptr):
+    """Host checks of the 1D model's entry points run before any HIP call."""
+    L = ns.lib()
+    p = None if ptr is None else ctypes.c_void_p(ptr)
+    assert L.ns1d_nonlinear(p, p, n, ct, batch, 0.0, None) == ns.NS_ERR_ARG
+    assert L.ns1d_step(p, n, ct, batch, 0.1, 1, 0, None) == ns.NS_ERR_ARG
+    assert L.ns_last_error(None)
+
+
+@pytest.mark.parametrize("dt,nsteps,scheme", [(0.0, 1, 0), (float("nan"), 1, 0), (0.1, -1, 0), (0.1, 1, 6),
+                                              (0.1, 1, -1)])
+def test_model1d_step_argument_errors(dt, nsteps, scheme):
+    L = ns.lib()
+    p = ctypes.c_void_p(256)
+    assert L.ns1d_step(p, 16, 1.0, 1, dt, nsteps, scheme, None) == ns.NS_ERR_ARG
+    assert L.ns1d_nonlinear(p, p, 16, 1.0, 1, float("inf"), None) == ns.NS_ERR_ARG
