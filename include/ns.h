@@ -184,7 +184,11 @@ ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps)
  * first-stage shifts for NS_PS_RANDOM, or NULL to draw them as
  * alpha_i = SplitMix64 uniform (cfg.seed, step0 + s, i); ignored by the other
  * variants.  step0 keys the random draws (shifts and forcing) of the first step,
- * so that runs can be split and resumed exactly.
+ * so that runs can be split and resumed exactly: nsteps steps in one call give
+ * bit-identical results to nsteps calls of one step.  In one call the Heun
+ * variants keep the intermediate states in the workspace (compact, aligned rows
+ * of the retained planes), so steps after the first read, and steps before the
+ * last write, less than a step of its own.
  *   exact:  S_h = E_{dt/2}(S0 + dt/2 A(S0)), S = E_dt S0 + dt E_{dt/2} A(S_h),
  *           A = 1/2 [N(.;0) + N(.;1/2)]
  *   heun:   S1 = E_dt(S0 + dt (N(S0;alpha) + O)),

@@ -13,10 +13,12 @@ __device__ __forceinline__ int shell_of(long long k2) {
 
 // Bin layout of one partial: [0, nsh) E, [nsh, 2nsh) D, [2nsh, 3nsh) T,
 // then 3 x h one-dimensional energies, then totals E, eps, H, T, nonfinite.
-// Pass 1: every block accumulates its grid-stride share of the modes into LDS
-// bins (FP64) and writes them to partials[block].
+// Pass 1: every wavefront takes whole k_z rows (fixed k_x, k_y) in a grid-stride
+// loop, the lanes along k_z; a row's share of the 1D spectra in k_x and k_y is
+// summed over the wavefront before its one LDS atomic per bin.  The block's bins
+// (FP64, in LDS) go to partials[block].
 template <typename R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_spectra(const Cx<R>* __restrict__ u, const Cx<R>* __restrict__ nh, double nu, int n, int h,
           int nsh, long long comp, double* __restrict__ partials) {
   extern __shared__ double bins[];
@@ -25,48 +27,55 @@ k_spectra(const Cx<R>* __restrict__ u, const Cx<R>* __restrict__ nh, double nu, 
   __syncthreads();
   double tE = 0, tD = 0, tH = 0, tT = 0;
   unsigned bad = 0;
-  const long long total = comp;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int kz = (int)(idx % h);
-    const long long r2 = idx / h;
-    const int yi = (int)(r2 % n), xi = (int)(r2 / n);
+  const int lane = threadIdx.x & 63;
+  const long long nrows = (long long)n * n;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long row = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < nrows; row += nwaves) {
+    const int yi = (int)(row % n), xi = (int)(row / n);
     const int kx = kval(xi, n), ky = kval(yi, n);
-    const double w = (kz == 0 || 2 * kz == n) ? 1.0 : 2.0;
-    const Cx<R> a0 = u[idx], a1 = u[comp + idx], a2 = u[2 * comp + idx];
-    double ar[3] = {(double)a0.re, (double)a1.re, (double)a2.re};
-    double ai[3] = {(double)a0.im, (double)a1.im, (double)a2.im};
-    bool fin = true;
-    for (int c = 0; c < 3; ++c) fin = fin && isfinite(ar[c]) && isfinite(ai[c]);
-    double t = 0.0;
-    if (nh != nullptr) {
-      for (int c = 0; c < 3; ++c) {
-        const Cx<R> b = nh[c * comp + idx];
-        fin = fin && isfinite((double)b.re) && isfinite((double)b.im);
-        t += ar[c] * (double)b.re + ai[c] * (double)b.im;
+    double erow = 0.0;
+    for (int kz = lane; kz < h; kz += 64) {
+      const long long idx = row * h + kz;
+      const double w = (kz == 0 || 2 * kz == n) ? 1.0 : 2.0;
+      const Cx<R> a0 = u[idx], a1 = u[comp + idx], a2 = u[2 * comp + idx];
+      double ar[3] = {(double)a0.re, (double)a1.re, (double)a2.re};
+      double ai[3] = {(double)a0.im, (double)a1.im, (double)a2.im};
+      bool fin = true;
+      for (int c = 0; c < 3; ++c) fin = fin && isfinite(ar[c]) && isfinite(ai[c]);
+      double t = 0.0;
+      if (nh != nullptr) {
+        for (int c = 0; c < 3; ++c) {
+          const Cx<R> b = nh[c * comp + idx];
+          fin = fin && isfinite((double)b.re) && isfinite((double)b.im);
+          t += ar[c] * (double)b.re + ai[c] * (double)b.im;
+        }
+        t *= w;
       }
-      t *= w;
+      if (!fin) { ++bad; continue; }
+      const double e = 0.5 * w * (ar[0] * ar[0] + ai[0] * ai[0] + ar[1] * ar[1] + ai[1] * ai[1] +
+                                  ar[2] * ar[2] + ai[2] * ai[2]);
+      if (e == 0.0 && t == 0.0) continue;
+      const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
+      const double d = 2.0 * nu * (double)k2 * e;
+      // helicity density: with u = a + i b, Re(conj(u).(i k x u)) = 2 k.(a x b), so
+      // 1/2 w Re(conj(u).omega) = w k.(a x b)
+      const double cxr = ar[1] * ai[2] - ar[2] * ai[1];
+      const double cyr = ar[2] * ai[0] - ar[0] * ai[2];
+      const double czr = ar[0] * ai[1] - ar[1] * ai[0];
+      const double hd = w * ((double)kx * cxr + (double)ky * cyr + (double)kz * czr);
+      const int s = shell_of(k2);
+      atomicAdd(&bins[s], e);
+      atomicAdd(&bins[nsh + s], d);
+      if (nh != nullptr) atomicAdd(&bins[2 * nsh + s], t);
+      atomicAdd(&bins[3 * nsh + 2 * h + kz], e);
+      erow += e;
+      tE += e; tD += d; tH += hd; tT += t;
     }
-    if (!fin) { ++bad; continue; }
-    const double e = 0.5 * w * (ar[0] * ar[0] + ai[0] * ai[0] + ar[1] * ar[1] + ai[1] * ai[1] +
-                                ar[2] * ar[2] + ai[2] * ai[2]);
-    if (e == 0.0 && t == 0.0) continue;
-    const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
-    const double d = 2.0 * nu * (double)k2 * e;
-    // helicity density: with u = a + i b, Re(conj(u).(i k x u)) = 2 k.(a x b), so
-    // 1/2 w Re(conj(u).omega) = w k.(a x b)
-    const double cxr = ar[1] * ai[2] - ar[2] * ai[1];
-    const double cyr = ar[2] * ai[0] - ar[0] * ai[2];
-    const double czr = ar[0] * ai[1] - ar[1] * ai[0];
-    const double hd = w * ((double)kx * cxr + (double)ky * cyr + (double)kz * czr);
-    const int s = shell_of(k2);
-    atomicAdd(&bins[s], e);
-    atomicAdd(&bins[nsh + s], d);
-    if (nh != nullptr) atomicAdd(&bins[2 * nsh + s], t);
-    atomicAdd(&bins[3 * nsh + abs(kx)], e);
-    atomicAdd(&bins[3 * nsh + h + abs(ky)], e);
-    atomicAdd(&bins[3 * nsh + 2 * h + kz], e);
-    tE += e; tD += d; tH += hd; tT += t;
+    for (int off = 32; off > 0; off >>= 1) erow += __shfl_down(erow, off);
+    if (lane == 0 && erow != 0.0) {
+      atomicAdd(&bins[3 * nsh + abs(kx)], erow);
+      atomicAdd(&bins[3 * nsh + h + abs(ky)], erow);
+    }
   }
   // totals: wave reduction then one LDS atomic per wave
   for (int off = 32; off > 0; off >>= 1) {
@@ -139,7 +148,7 @@ __device__ __forceinline__ int forcing_mode(int i, int* kx, int* ky, int* kz) {
 // force[c][k_x+3][k_y+3][k_z] (k_z <= 3).
 template <typename R>
 __global__ void __launch_bounds__(64)
-k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int h, long long comp,
+k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int pitch, long long comp,
           uint64_t seed, long long step, double dt, double inj) {
   __shared__ double gre[48][3], gim[48][3], pb[48], pg[48];
   __shared__ double amp;
@@ -165,7 +174,7 @@ k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int h, 
     vr[0] -= kx * dr; vr[1] -= ky * dr; vr[2] -= kz * dr;
     vi[0] -= kx * di; vi[1] -= ky * di; vi[2] -= kz * di;
     // B and G contributions of the stored half-spectrum entries of this mode
-    const long long idx = ((long long)((kx + n) % n) * n + (ky + n) % n) * h + kz;
+    const long long idx = ((long long)((kx + n) % n) * n + (ky + n) % n) * pitch + kz;
     double b = 0, g2 = 0;
     const double w = (kz == 0) ? 1.0 : 2.0;
     for (int c = 0; c < 3; ++c) {
@@ -174,7 +183,7 @@ k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int h, 
       g2 += w * (vr[c] * vr[c] + vi[c] * vi[c]);
     }
     if (kz == 0) {  // the partner -k holds conj(g)
-      const long long idp = ((long long)((-kx + n) % n) * n + (-ky + n) % n) * h;
+      const long long idp = ((long long)((-kx + n) % n) * n + (-ky + n) % n) * pitch;
       for (int c = 0; c < 3; ++c) {
         const Cx<R> a = u[c * comp + idp];
         b += (double)a.re * vr[c] - (double)a.im * vi[c];

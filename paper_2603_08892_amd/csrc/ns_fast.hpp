@@ -338,8 +338,10 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   Cx<float> phyz = cx(1.f, 0.f);
   // stage operands, read per chunk of points before that chunk's stores (out0 may
   // alias an operand, which keeps the compiler from hoisting loads above stores):
-  // all points for one-operand stages, half of them for two-operand ones; the first
-  // chunk is read before the last transform so that its latency overlaps it
+  // half of the points per chunk for two-operand stages, and for one-operand
+  // stages at N <= 128 (fewer registers, four waves per SIMD instead of three;
+  // measured faster there, slower at N = 256); the first chunk is read before the
+  // last transform so that its latency overlaps it
   constexpr bool need0 = (OP == OP_HEUN1 || OP == OP_EX1B || OP == OP_EX2B || OP == OP_RK4_0 ||
                           OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_MID1 || OP == OP_MID2 ||
                           OP == OP_EUL || OP == OP_EULAV);
@@ -347,7 +349,7 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
                           OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3 || OP == OP_ACC ||
                           OP == OP_EULAV);
   constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
-  constexpr int CH = (need0 && need1) ? EPT / 2 : EPT;
+  constexpr int CH = ((need0 && need1) || ((need0 || need1) && N <= 128)) ? EPT / 2 : EPT;
   const LineTest keep = line_test(g, ky, kz);
   const bool line_kept = active && kz < g.kzn;
   Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];

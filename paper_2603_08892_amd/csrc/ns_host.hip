@@ -34,6 +34,7 @@ constexpr int kEpt = 8;     // points per thread in the strided passes
 constexpr int kEptZ = 16;   // points per thread in the contiguous (z) pass
 constexpr size_t kAlign = 256;
 constexpr int kSpecBlocks = 256;
+constexpr int kSpecThreads = 1024;  // 16 wavefronts per block, one block per CU
 
 thread_local std::string g_last_error;
 
@@ -628,25 +629,32 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     }
     double be[3];
     for (int j = 0; j < 3; ++j) be[j] = std::fmod(al[j] + 0.5, 1.0);
+    // Between the steps of one call the state stays in sb (compact rows, retained
+    // modes only): the first step reads the caller's array, the last writes it back
+    // whole.  Step i reads its state from sb and overwrites it with S1 element by
+    // element (S0 is no longer needed once the partial update is in ab).
+    const bool first = (i == 0), last = (i == nsteps - 1);
+    Cx<R>* x = first ? s0 : p.sb;
+    const ns::Lay lx = first ? U : K;
     EpiArgs<R> a = epi<R>(c, 0);
     a.dt = R(dt);
-    a.in0 = s0;
-    a.li0 = U;
+    a.in0 = x;
+    a.li0 = lx;
     a.out0 = p.ab;
     a.out1 = p.sb;
     if (fo != nullptr) {
       const Geom& g = c->lay.g;
-      hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(64), 0, c->stream, s0, p.force, g.n, g.h,
-                         g.comp, fo->seed, step0 + i, dt, fo->injection);
+      hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(64), 0, c->stream, x, p.force, g.n, lx.pitch,
+                         lx.cs, fo->seed, step0 + i, dt, fo->injection);
       if ((st = hip_check(c, hipGetLastError(), "k_forcing launch")) != NS_OK) return st;
       a.force = p.force;
     }
-    if ((st = eval<R, ns::OP_HEUN1>(c, s0, U, al, a)) != NS_OK) return st;
-    EpiArgs<R> f = epi<R>(c, 1);
+    if ((st = eval<R, ns::OP_HEUN1>(c, x, lx, al, a)) != NS_OK) return st;
+    EpiArgs<R> f = epi<R>(c, last ? 1 : 0);
     f.dt = R(dt);
     f.in1 = p.ab;
-    f.out0 = s0;
-    f.lo0 = U;
+    f.out0 = last ? s0 : p.sb;
+    f.lo0 = last ? U : K;
     if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f)) != NS_OK) return st;
   }
   return NS_OK;
@@ -783,7 +791,7 @@ ns_status spectra_t(ns_ctx* c, const void* u, const void* nh, ns_spectra_out* ou
   const size_t lds = (size_t)l.nbins * sizeof(double);
   hipError_t e = allow_lds(ns::k_spectra<R>, lds);
   if (e != hipSuccess) return hip_check(c, e, "k_spectra attribute");
-  hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(256), lds, c->stream,
+  hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(kSpecThreads), lds, c->stream,
                      static_cast<const Cx<R>*>(u), static_cast<const Cx<R>*>(nh), c->cfg.nu, l.g.n,
                      l.g.h, l.nsh, l.g.comp, p.spec);
   hipLaunchKernelGGL(ns::k_spectra_sum, dim3((l.nbins + 7) / 8), dim3(256), 0, c->stream, p.spec,

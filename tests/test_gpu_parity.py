@@ -345,3 +345,30 @@ def test_specialised_passes_match_generic(n, ct, mask):
                 s_.step_ps(ud, dt, 2, scheme)
         a, b = _host(ua), _host(ub)
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-6, scheme
+
+
+@pytest.mark.parametrize("n,ct,prec,variant,forced", [(24, 1.0, "fp64", "random", True), (24, 1.0, "fp64", "approx", False),
+                                                      (128, 1.0, "fp32", "random", True), (128, 1.0, "fp32", "approx", False),
+                                                      (192, 2 / 3, "fp32", "random", False)])
+def test_multi_step_call_equals_single_steps(n, ct, prec, variant, forced):
+    """k steps in one call (the Heun variants keep the state in the workspace between
+    them) are bit-identical to k calls of one step, and both match the oracle."""
+    print(f"[multi-step] n={n} {prec} {variant} forced={forced}", flush=True)
+    nu, dt, k = 0.01, 2e-3, 4
+    s = _solver(n, ct, prec=prec, nu=nu, seed=31)
+    u = _rep(_field(n, ct, "sphere", 500 + n, energy=0.5), prec)
+    fo = {"seed": 3, "injection": 1.0} if forced else None
+    a, b = s.to_device(u), s.to_device(u)
+    s.step_ps(a, dt, k, variant, forcing=fo, step0=9)
+    for i in range(k):
+        s.step_ps(b, dt, 1, variant, forcing=fo, step0=9 + i)
+    ga, gb = _host(a), _host(b)
+    assert np.array_equal(ga, gb)
+    if n <= 24:
+        model = onl.NSModel(n, nu, grid.mask(n, ct))
+        want = u
+        for i in range(k):
+            al = oforcing.random_shift(31, 9 + i) if variant == "random" else (0, 0, 0)
+            o = oforcing.forcing(want, dt, 3, 9 + i) if forced else None
+            want = schemes.ps_heun(model, want, dt, al, forcing=o)
+        _check(ga, want, prec, "multi-step")
