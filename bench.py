@@ -117,14 +117,21 @@ def run_scheme(torch, ns, inputs, name, n, ct, steps, warmup, timing=False):
             s.step_ps(u, DT, k, "random", step0=i)
 
     def run(nsteps):
-        # a time loop: the steps between two spectra in one call each
-        i = 0
+        # a time loop: the steps between two spectra in one call each; the host collects
+        # each spectra result once the next steps are queued behind it
+        i, pending = 0, False
         while i < nsteps:
             k = min(SPEC_EVERY - i % SPEC_EVERY, nsteps - i)
             advance(i, k)
             i += k
+            if pending:
+                s.spectra_wait()
+                pending = False
             if i % SPEC_EVERY == 0:
-                s.spectra(u)
+                s.spectra_async(u)
+                pending = True
+        if pending:
+            s.spectra_wait()
 
     run(warmup)
     u.copy_(u0)

@@ -174,7 +174,9 @@ ns_status ns_nonlinear(ns_ctx* ctx, const void* u_hat, void* n_hat, const double
 
 /* nsteps steps of classical RK4 in integrating-factor (Lawson) form, unshifted
  * (the 2/3-truncation baseline of Tables I-V when cfg.ct = 2/3), in place on the
- * state u_hat.  dt > 0, nsteps >= 0. */
+ * state u_hat.  dt > 0, nsteps >= 0.  As for ns_step_rk2_phaseshift, the
+ * intermediate states of one call stay in the workspace; nsteps steps in one call
+ * are bit-identical to nsteps calls of one step. */
 ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps);
 
 /* nsteps steps of phase-shift RK2 (Eqs. Rogallo1981 and its 3D form; split
@@ -185,10 +187,10 @@ ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps)
  * alpha_i = SplitMix64 uniform (cfg.seed, step0 + s, i); ignored by the other
  * variants.  step0 keys the random draws (shifts and forcing) of the first step,
  * so that runs can be split and resumed exactly: nsteps steps in one call give
- * bit-identical results to nsteps calls of one step.  In one call the Heun
- * variants keep the intermediate states in the workspace (compact, aligned rows
- * of the retained planes), so steps after the first read, and steps before the
- * last write, less than a step of its own.
+ * bit-identical results to nsteps calls of one step.  In one call every variant
+ * keeps the intermediate states in the workspace (compact, aligned rows of the
+ * retained planes), so steps after the first read, and steps before the last
+ * write, less than a step of its own.
  *   exact:  S_h = E_{dt/2}(S0 + dt/2 A(S0)), S = E_dt S0 + dt E_{dt/2} A(S_h),
  *           A = 1/2 [N(.;0) + N(.;1/2)]
  *   heun:   S1 = E_dt(S0 + dt (N(S0;alpha) + O)),
@@ -205,6 +207,16 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
  * Returns NS_ERR_NONFINITE (outputs still written) if any entry of u_hat or
  * n_hat is NaN or Inf. */
 ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out);
+
+/* The same in two halves, so that a time loop keeps the GPU busy while the host
+ * waits: ns_spectra_async enqueues the reduction of u_hat (and n_hat) as they are
+ * at that point of the stream, with its copy into pinned host memory the library
+ * allocates on first use; ns_spectra_wait waits for that reduction only (not for
+ * work enqueued after it) and fills out like ns_spectra.  One reduction is in
+ * flight per context: a later ns_spectra_async or ns_spectra replaces one not yet
+ * waited for.  ns_spectra_wait with nothing in flight returns NS_ERR_STATE. */
+ns_status ns_spectra_async(ns_ctx* ctx, const void* u_hat, const void* n_hat);
+ns_status ns_spectra_wait(ns_ctx* ctx, ns_spectra_out* out);
 
 /* Transpose of the linearised phase-shift RK2 step at state u_hat0 (no forcing):
  * lam holds dJ/dS_{n+1} on entry and dJ/dS_n on return, both with respect to the

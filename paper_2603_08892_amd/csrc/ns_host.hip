@@ -230,7 +230,9 @@ struct ns_ctx {
   Layout lay;
   char* ws;
   std::string err;
-  std::vector<double> host_spec;
+  double* pin_spec = nullptr;    // pinned host copy of the last spectra reduction
+  hipEvent_t spec_ev = nullptr;  // recorded after that copy
+  bool spec_pending = false;     // a reduction was enqueued and not yet waited for
   int fast = 0;       // N of the specialised FP32 passes in use (0: generic passes)
   double etab_dt = -1.0;  // dt of the integrating-factor tables now in the workspace
   // per-pass timing: events[2 i], events[2 i + 1] bracket launch i of pass tpass[i]
@@ -240,6 +242,8 @@ struct ns_ctx {
   size_t tused = 0;
   ~ns_ctx() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (spec_ev) (void)hipEventDestroy(spec_ev);
+    if (pin_spec) (void)hipHostFree(pin_spec);
   }
 };
 
@@ -490,22 +494,29 @@ ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
   const ns::Lay U = user_lay(c->lay), K = compact_lay(c->lay);
   ns_status st = etab<R>(c, dt);
   if (st != NS_OK) return st;
+  // Between the steps of one call the state stays in scratch fields 6..8 (compact
+  // rows, retained modes only; the forward passes use fields 0..5): the first step
+  // reads the caller's array, the last writes it back whole.
+  Cx<R>* xs = p.W + 6 * c->lay.g.wcomp;
   for (int i = 0; i < nsteps; ++i) {
+    const bool first = (i == 0), last = (i == nsteps - 1);
+    Cx<R>* x = first ? s0 : xs;
+    const ns::Lay lx = first ? U : K;
     EpiArgs<R> a = epi<R>(c, 0);
     a.dt = R(dt);
-    a.in0 = s0;
-    a.li0 = U;
+    a.in0 = x;
+    a.li0 = lx;
     a.in1 = p.ab;
     a.out0 = p.ab;
     a.out1 = p.sb;
-    if ((st = eval<R, ns::OP_RK4_0>(c, s0, U, nullptr, a)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_RK4_0>(c, x, lx, nullptr, a)) != NS_OK) return st;
     if ((st = eval<R, ns::OP_RK4_1>(c, p.sb, K, nullptr, a)) != NS_OK) return st;
     if ((st = eval<R, ns::OP_RK4_2>(c, p.sb, K, nullptr, a)) != NS_OK) return st;
-    EpiArgs<R> f = epi<R>(c, 1);
+    EpiArgs<R> f = epi<R>(c, last ? 1 : 0);
     f.dt = R(dt);
     f.in1 = p.ab;
-    f.out0 = s0;
-    f.lo0 = U;
+    f.out0 = last ? s0 : xs;
+    f.lo0 = last ? U : K;
     if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, K, nullptr, f)) != NS_OK) return st;
   }
   return NS_OK;
@@ -532,94 +543,85 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
   ns_status st = etab<R>(c, dt);
   if (st != NS_OK) return st;
   const double zero[3] = {0, 0, 0}, half[3] = {0.5, 0.5, 0.5};
+  // Between the steps of one call the state stays in scratch fields 6..8 (compact
+  // rows, retained modes only; the forward passes use fields 0..5): the first step
+  // reads the caller's array (x), the last writes it back whole (y).
+  Cx<R>* xs = p.W + 6 * c->lay.g.wcomp;
   for (int i = 0; i < nsteps; ++i) {
+    const bool first = (i == 0), last = (i == nsteps - 1);
+    Cx<R>* x = first ? s0 : xs;
+    Cx<R>* y = last ? s0 : xs;
+    const ns::Lay lx = first ? U : K, ly = last ? U : K;
+    const int fy = last ? 1 : 0;
     if (variant == NS_RK2) {
       // midpoint RK2 without shifts: S_h = E_h (S0 + dt/2 N(S0)); S = E_dt S0 + dt E_h N(S_h)
       EpiArgs<R> a = epi<R>(c, 0);
       a.dt = R(dt);
-      a.in0 = s0;
-      a.li0 = U;
+      a.in0 = x;
+      a.li0 = lx;
       a.out0 = p.sb;
-      if ((st = eval<R, ns::OP_MID1>(c, s0, U, zero, a)) != NS_OK) return st;
-      EpiArgs<R> f = epi<R>(c, 1);
+      if ((st = eval<R, ns::OP_MID1>(c, x, lx, zero, a)) != NS_OK) return st;
+      EpiArgs<R> f = epi<R>(c, fy);
       f.dt = R(dt);
-      f.in0 = s0;
-      f.li0 = U;
-      f.out0 = s0;
-      f.lo0 = U;
+      f.in0 = x;
+      f.li0 = lx;
+      f.out0 = y;
+      f.lo0 = ly;
       if ((st = eval<R, ns::OP_MID2>(c, p.sb, K, zero, f)) != NS_OK) return st;
       continue;
     }
     if (variant == NS_EULER || variant == NS_EULER_PS) {
       // S = E_dt (S0 + dt N_a) with N_a = N(S0) or the two-shift average
-      EpiArgs<R> f = epi<R>(c, 1);
+      EpiArgs<R> f = epi<R>(c, fy);
       f.dt = R(dt);
-      f.in0 = s0;
-      f.li0 = U;
-      f.out0 = s0;
-      f.lo0 = U;
+      f.in0 = x;
+      f.li0 = lx;
+      f.out0 = y;
+      f.lo0 = ly;
       if (variant == NS_EULER) {
-        if ((st = eval<R, ns::OP_EUL>(c, s0, U, zero, f)) != NS_OK) return st;
+        if ((st = eval<R, ns::OP_EUL>(c, x, lx, zero, f)) != NS_OK) return st;
         continue;
       }
       EpiArgs<R> a = epi<R>(c, 0);
       a.out0 = p.ab;
-      if ((st = eval<R, ns::OP_STORE>(c, s0, U, zero, a)) != NS_OK) return st;
+      if ((st = eval<R, ns::OP_STORE>(c, x, lx, zero, a)) != NS_OK) return st;
       f.in1 = p.ab;
-      if ((st = eval<R, ns::OP_EULAV>(c, s0, U, half, f)) != NS_OK) return st;
+      if ((st = eval<R, ns::OP_EULAV>(c, x, lx, half, f)) != NS_OK) return st;
       continue;
     }
-    if (variant == NS_PS_EXACT8) {
-      // midpoint RK2, every evaluation averaged over the eight shifts in {0, 1/2}^3:
-      // the first seven are summed into ab, the eighth closes the stage with w = 1/8
+    if (variant == NS_PS_EXACT || variant == NS_PS_EXACT8) {
+      // midpoint RK2 with every evaluation the average over ns shifts: the first
+      // ns - 1 are summed into ab, the last closes the stage with weight w = 1/ns
+      // (ns = 2: shifts 0 and (1/2,1/2,1/2); ns = 8: the shifts in {0, 1/2}^3)
+      const double s2[2][3] = {{0, 0, 0}, {0.5, 0.5, 0.5}};
       const double s8[8][3] = {{0, 0, 0},     {0, 0, 0.5},   {0, 0.5, 0},   {0, 0.5, 0.5},
                                {0.5, 0, 0},   {0.5, 0, 0.5}, {0.5, 0.5, 0}, {0.5, 0.5, 0.5}};
+      const int ns = variant == NS_PS_EXACT ? 2 : 8;
+      const double(*sh)[3] = variant == NS_PS_EXACT ? s2 : s8;
       for (int stage = 0; stage < 2; ++stage) {
-        const Cx<R>* x = stage == 0 ? s0 : p.sb;
-        const ns::Lay lx = stage == 0 ? U : K;
+        const Cx<R>* z = stage == 0 ? x : p.sb;
+        const ns::Lay lz = stage == 0 ? lx : K;
         EpiArgs<R> a = epi<R>(c, 0);
         a.out0 = p.ab;
-        if ((st = eval<R, ns::OP_STORE>(c, x, lx, s8[0], a)) != NS_OK) return st;
+        if ((st = eval<R, ns::OP_STORE>(c, z, lz, sh[0], a)) != NS_OK) return st;
         a.in1 = p.ab;
-        for (int j = 1; j < 7; ++j)
-          if ((st = eval<R, ns::OP_ACC>(c, x, lx, s8[j], a)) != NS_OK) return st;
-        EpiArgs<R> f = epi<R>(c, stage);
+        for (int j = 1; j < ns - 1; ++j)
+          if ((st = eval<R, ns::OP_ACC>(c, z, lz, sh[j], a)) != NS_OK) return st;
+        EpiArgs<R> f = epi<R>(c, stage == 0 ? 0 : fy);
         f.dt = R(dt);
-        f.w = R(0.125);
-        f.in0 = s0;
-        f.li0 = U;
+        f.w = R(1.0 / ns);
+        f.in0 = x;
+        f.li0 = lx;
         f.in1 = p.ab;
         if (stage == 0) {
           f.out0 = p.sb;
-          if ((st = eval<R, ns::OP_EX1B>(c, x, lx, s8[7], f)) != NS_OK) return st;
+          if ((st = eval<R, ns::OP_EX1B>(c, z, lz, sh[ns - 1], f)) != NS_OK) return st;
         } else {
-          f.out0 = s0;
-          f.lo0 = U;
-          if ((st = eval<R, ns::OP_EX2B>(c, x, lx, s8[7], f)) != NS_OK) return st;
+          f.out0 = y;
+          f.lo0 = ly;
+          if ((st = eval<R, ns::OP_EX2B>(c, z, lz, sh[ns - 1], f)) != NS_OK) return st;
         }
       }
-      continue;
-    }
-    if (variant == NS_PS_EXACT) {
-      EpiArgs<R> a = epi<R>(c, 0);
-      a.dt = R(dt);
-      a.out0 = p.ab;
-      if ((st = eval<R, ns::OP_STORE>(c, s0, U, zero, a)) != NS_OK) return st;
-      a.in0 = s0;
-      a.li0 = U;
-      a.in1 = p.ab;
-      a.out0 = p.sb;
-      if ((st = eval<R, ns::OP_EX1B>(c, s0, U, half, a)) != NS_OK) return st;
-      a.out0 = p.ab;
-      if ((st = eval<R, ns::OP_STORE>(c, p.sb, K, zero, a)) != NS_OK) return st;
-      EpiArgs<R> f = epi<R>(c, 1);
-      f.dt = R(dt);
-      f.in0 = s0;
-      f.li0 = U;
-      f.in1 = p.ab;
-      f.out0 = s0;
-      f.lo0 = U;
-      if ((st = eval<R, ns::OP_EX2B>(c, p.sb, K, half, f)) != NS_OK) return st;
       continue;
     }
     double al[3] = {0, 0, 0};
@@ -629,13 +631,6 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     }
     double be[3];
     for (int j = 0; j < 3; ++j) be[j] = std::fmod(al[j] + 0.5, 1.0);
-    // Between the steps of one call the state stays in sb (compact rows, retained
-    // modes only): the first step reads the caller's array, the last writes it back
-    // whole.  Step i reads its state from sb and overwrites it with S1 element by
-    // element (S0 is no longer needed once the partial update is in ab).
-    const bool first = (i == 0), last = (i == nsteps - 1);
-    Cx<R>* x = first ? s0 : p.sb;
-    const ns::Lay lx = first ? U : K;
     EpiArgs<R> a = epi<R>(c, 0);
     a.dt = R(dt);
     a.in0 = x;
@@ -650,11 +645,11 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
       a.force = p.force;
     }
     if ((st = eval<R, ns::OP_HEUN1>(c, x, lx, al, a)) != NS_OK) return st;
-    EpiArgs<R> f = epi<R>(c, last ? 1 : 0);
+    EpiArgs<R> f = epi<R>(c, fy);
     f.dt = R(dt);
     f.in1 = p.ab;
-    f.out0 = last ? s0 : p.sb;
-    f.lo0 = last ? U : K;
+    f.out0 = y;
+    f.lo0 = ly;
     if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f)) != NS_OK) return st;
   }
   return NS_OK;
@@ -784,10 +779,23 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
   return adj_eval<R, ns::AOP_HEUN>(c, u0, U, al, l2, b);
 }
 
+// Enqueue the reduction and its copy into pinned host memory, then record an
+// event: the result can be waited for without waiting for later work.
 template <typename R>
-ns_status spectra_t(ns_ctx* c, const void* u, const void* nh, ns_spectra_out* out) {
+ns_status spectra_enqueue_t(ns_ctx* c, const void* u, const void* nh) {
   const Layout& l = c->lay;
   Ptrs<R> p = ptrs<R>(c);
+  ns_status st;
+  if (c->pin_spec == nullptr) {
+    void* h = nullptr;
+    if ((st = hip_check(c, hipHostMalloc(&h, (size_t)l.nbins * sizeof(double), hipHostMallocDefault),
+                        "pinned spectra buffer")) != NS_OK)
+      return st;
+    c->pin_spec = static_cast<double*>(h);
+  }
+  if (c->spec_ev == nullptr &&
+      (st = hip_check(c, hipEventCreateWithFlags(&c->spec_ev, hipEventDisableTiming), "spectra event")) != NS_OK)
+    return st;
   const size_t lds = (size_t)l.nbins * sizeof(double);
   hipError_t e = allow_lds(ns::k_spectra<R>, lds);
   if (e != hipSuccess) return hip_check(c, e, "k_spectra attribute");
@@ -796,15 +804,22 @@ ns_status spectra_t(ns_ctx* c, const void* u, const void* nh, ns_spectra_out* ou
                      l.g.h, l.nsh, l.g.comp, p.spec);
   hipLaunchKernelGGL(ns::k_spectra_sum, dim3((l.nbins + 7) / 8), dim3(256), 0, c->stream, p.spec,
                      kSpecBlocks, l.nbins, p.specout);
-  ns_status st = hip_check(c, hipGetLastError(), "spectra launch");
+  if ((st = hip_check(c, hipGetLastError(), "spectra launch")) != NS_OK) return st;
+  if ((st = hip_check(c, hipMemcpyAsync(c->pin_spec, p.specout, l.nbins * sizeof(double),
+                                        hipMemcpyDeviceToHost, c->stream), "spectra copy")) != NS_OK)
+    return st;
+  if ((st = hip_check(c, hipEventRecord(c->spec_ev, c->stream), "spectra event record")) != NS_OK) return st;
+  c->spec_pending = true;
+  return NS_OK;
+}
+
+ns_status spectra_wait(ns_ctx* c, ns_spectra_out* out) {
+  if (!c->spec_pending) return fail(c, NS_ERR_STATE, "no spectra reduction in flight");
+  ns_status st = hip_check(c, hipEventSynchronize(c->spec_ev), "spectra wait");
   if (st != NS_OK) return st;
-  c->host_spec.resize(l.nbins);
-  st = hip_check(c, hipMemcpyAsync(c->host_spec.data(), p.specout, l.nbins * sizeof(double),
-                                   hipMemcpyDeviceToHost, c->stream), "spectra copy");
-  if (st != NS_OK) return st;
-  st = hip_check(c, hipStreamSynchronize(c->stream), "spectra synchronize");
-  if (st != NS_OK) return st;
-  const double* b = c->host_spec.data();
+  c->spec_pending = false;
+  const Layout& l = c->lay;
+  const double* b = c->pin_spec;
   const int nsh = l.nsh, h = l.g.h;
   if (out->e_shell) std::memcpy(out->e_shell, b, nsh * sizeof(double));
   if (out->d_shell) std::memcpy(out->d_shell, b + nsh, nsh * sizeof(double));
@@ -1008,13 +1023,25 @@ ns_status ns1d_step(void* s_hat, int32_t n, double ct, int32_t batch, double dt,
   return launch1d(a, batch, stream);
 }
 
+ns_status ns_spectra_async(ns_ctx* ctx, const void* u_hat, const void* n_hat) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!aligned(u_hat) || (n_hat != nullptr && !aligned(n_hat)))
+    return fail(ctx, NS_ERR_ARG, "u_hat (and n_hat if given) must be 256-byte aligned device pointers");
+  return ctx->cfg.precision == NS_FP32 ? spectra_enqueue_t<float>(ctx, u_hat, n_hat)
+                                       : spectra_enqueue_t<double>(ctx, u_hat, n_hat);
+}
+
+ns_status ns_spectra_wait(ns_ctx* ctx, ns_spectra_out* out) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!out) return fail(ctx, NS_ERR_ARG, "out is NULL");
+  return spectra_wait(ctx, out);
+}
+
 ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out) {
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
   if (!out) return fail(ctx, NS_ERR_ARG, "out is NULL");
-  if (!aligned(u_hat) || (n_hat != nullptr && !aligned(n_hat)))
-    return fail(ctx, NS_ERR_ARG, "u_hat (and n_hat if given) must be 256-byte aligned device pointers");
-  return ctx->cfg.precision == NS_FP32 ? spectra_t<float>(ctx, u_hat, n_hat, out)
-                                       : spectra_t<double>(ctx, u_hat, n_hat, out);
+  ns_status st = ns_spectra_async(ctx, u_hat, n_hat);
+  return st != NS_OK ? st : spectra_wait(ctx, out);
 }
 
 ns_status ns_timing_enable(ns_ctx* ctx, int32_t enable) {

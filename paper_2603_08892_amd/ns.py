@@ -31,7 +31,7 @@ VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM
 ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns_init", "ns_destroy",
                  "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
                  "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift", "ns_timing_enable",
-                 "ns_timing_read", "ns1d_nonlinear", "ns1d_step")
+                 "ns_timing_read", "ns1d_nonlinear", "ns1d_step", "ns_spectra_async", "ns_spectra_wait")
 PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue")
 
 
@@ -85,6 +85,8 @@ def lib():
         "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P]),
         "ns_timing_enable": (I32, [P, I32]),
         "ns_timing_read": (I32, [P, P, P]),
+        "ns_spectra_async": (I32, [P, P, P]),
+        "ns_spectra_wait": (I32, [P, ctypes.POINTER(NSSpectraOut)]),
         "ns1d_nonlinear": (I32, [P, P, I32, D, I32, D, P]),
         "ns1d_step": (I32, [P, I32, D, I32, D, I32, I32, P]),
     }
@@ -211,19 +213,36 @@ class Solver:
                                                  VARIANTS[variant], ap, fo, int(step0)))
         return u
 
-    def spectra(self, u, n_hat=None, check_finite=True):
-        self._sync_stream()
+    def _spectra_out(self):
         nsh, h = self.nshells, self.n // 2 + 1
         out = {"e_shell": np.zeros(nsh), "d_shell": np.zeros(nsh), "t_shell": np.zeros(nsh),
                "e_1d": np.zeros((3, h)), "totals": np.zeros(5)}
         so = NSSpectraOut(*[out[k].ctypes.data_as(ctypes.c_void_p) for k in
                             ("e_shell", "d_shell", "t_shell", "e_1d", "totals")])
-        st = lib().ns_spectra(self.ctx, self._field(u, "u"),
-                              None if n_hat is None else self._field(n_hat, "n_hat"), ctypes.byref(so))
+        return out, so
+
+    def _spectra_status(self, st, out, check_finite):
         if st == NS_ERR_NONFINITE and not check_finite:
             return out
         self._check(st)
         return out
+
+    def spectra(self, u, n_hat=None, check_finite=True):
+        self._sync_stream()
+        out, so = self._spectra_out()
+        st = lib().ns_spectra(self.ctx, self._field(u, "u"),
+                              None if n_hat is None else self._field(n_hat, "n_hat"), ctypes.byref(so))
+        return self._spectra_status(st, out, check_finite)
+
+    def spectra_async(self, u, n_hat=None):
+        """Enqueue the spectra of u (as it is at this point of the stream); spectra_wait returns them."""
+        self._sync_stream()
+        self._check(lib().ns_spectra_async(self.ctx, self._field(u, "u"),
+                                           None if n_hat is None else self._field(n_hat, "n_hat")))
+
+    def spectra_wait(self, check_finite=True):
+        out, so = self._spectra_out()
+        return self._spectra_status(lib().ns_spectra_wait(self.ctx, ctypes.byref(so)), out, check_finite)
 
     def vjp_ps(self, u0, lam, dt, variant="random", alpha=None):
         """In place: lam <- (dS_new/dS_0)^T lam for one unforced phase-shift RK2 step at u0."""

@@ -75,19 +75,34 @@ def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=20
     nsteps = int(round(t_end / dt))
     first, stride = int(round(t_start / dt)), max(1, int(round(every / dt)))
     times, spec = [], []
+
+    def advance(i, k):
+        if scheme == "rk4":
+            s.step_rk4(u, dt, k)
+        elif scheme == "random":
+            s.step_ps(u, dt, k, "random", step0=i)
+        else:
+            s.step_ps(u, dt, k, scheme)
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(nsteps):
-        if scheme == "rk4":
-            s.step_rk4(u, dt, 1)
-        elif scheme == "random":
-            s.step_ps(u, dt, 1, "random", step0=i)
-        else:
-            s.step_ps(u, dt, 1, scheme)
-        k = i + 1
+    # the steps up to the next sample in one call; each sample is collected once the
+    # following steps are queued behind it
+    k, pending = 0, False
+    while k < nsteps:
+        nxt = first if k < first else first + ((k - first) // stride + 1) * stride
+        nxt = min(max(nxt, k + 1), nsteps)
+        advance(k, nxt - k)
+        k = nxt
+        if pending:
+            spec.append(s.spectra_wait()["e_1d"][:, :kmax + 1].copy())
+            pending = False
         if k >= first and (k - first) % stride == 0:
-            spec.append(s.spectra(u)["e_1d"][:, :kmax + 1].copy())
+            s.spectra_async(u)
             times.append(k * dt)
+            pending = True
+    if pending:
+        spec.append(s.spectra_wait()["e_1d"][:, :kmax + 1].copy())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return np.array(times), np.array(spec), wall

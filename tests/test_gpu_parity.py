@@ -347,12 +347,14 @@ def test_specialised_passes_match_generic(n, ct, mask):
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-6, scheme
 
 
-@pytest.mark.parametrize("n,ct,prec,variant,forced", [(24, 1.0, "fp64", "random", True), (24, 1.0, "fp64", "approx", False),
-                                                      (128, 1.0, "fp32", "random", True), (128, 1.0, "fp32", "approx", False),
-                                                      (192, 2 / 3, "fp32", "random", False)])
+@pytest.mark.parametrize("n,ct,prec,variant,forced", [
+    (24, 1.0, "fp64", "random", True), (24, 1.0, "fp64", "approx", False), (24, 1.0, "fp64", "exact", False),
+    (24, 1.0, "fp64", "rk2", False), (24, 1.0, "fp64", "euler", False), (24, 1.0, "fp64", "euler_ps", False),
+    (24, 1.0, "fp64", "exact8", False), (128, 1.0, "fp32", "random", True), (128, 1.0, "fp32", "approx", False),
+    (128, 1.0, "fp32", "exact", False), (192, 2 / 3, "fp32", "random", False), (64, 1.0, "fp32", "exact8", False)])
 def test_multi_step_call_equals_single_steps(n, ct, prec, variant, forced):
-    """k steps in one call (the Heun variants keep the state in the workspace between
-    them) are bit-identical to k calls of one step, and both match the oracle."""
+    """k steps in one call (the state stays in the workspace between them) are
+    bit-identical to k calls of one step, and both match the oracle."""
     print(f"[multi-step] n={n} {prec} {variant} forced={forced}", flush=True)
     nu, dt, k = 0.01, 2e-3, 4
     s = _solver(n, ct, prec=prec, nu=nu, seed=31)
@@ -368,7 +370,52 @@ def test_multi_step_call_equals_single_steps(n, ct, prec, variant, forced):
         model = onl.NSModel(n, nu, grid.mask(n, ct))
         want = u
         for i in range(k):
-            al = oforcing.random_shift(31, 9 + i) if variant == "random" else (0, 0, 0)
-            o = oforcing.forcing(want, dt, 3, 9 + i) if forced else None
-            want = schemes.ps_heun(model, want, dt, al, forcing=o)
+            if variant in ("random", "approx"):
+                al = oforcing.random_shift(31, 9 + i) if variant == "random" else (0, 0, 0)
+                o = oforcing.forcing(want, dt, 3, 9 + i) if forced else None
+                want = schemes.ps_heun(model, want, dt, al, forcing=o)
+            else:
+                want = _oracle_step(model, want, dt, variant)
         _check(ga, want, prec, "multi-step")
+
+
+@pytest.mark.parametrize("n,ct,prec", [(24, 2 / 3, "fp64"), (192, 2 / 3, "fp32")])
+def test_multi_step_rk4_call_equals_single_steps(n, ct, prec):
+    print(f"[multi-step rk4] n={n} {prec}", flush=True)
+    nu, dt, k = 0.01, 2e-3, 3
+    s = _solver(n, ct, prec=prec, nu=nu, seed=31)
+    u = _rep(_field(n, ct, "sphere", 700 + n, energy=0.5), prec)
+    a, b = s.to_device(u), s.to_device(u)
+    s.step_rk4(a, dt, k)
+    for _ in range(k):
+        s.step_rk4(b, dt, 1)
+    assert np.array_equal(_host(a), _host(b))
+    if n <= 24:
+        model = onl.NSModel(n, nu, grid.mask(n, ct))
+        want = u
+        for _ in range(k):
+            want = schemes.rk4(model, want, dt)
+        _check(_host(a), want, prec, "multi-step rk4")
+
+
+def test_spectra_async_sees_the_state_at_enqueue():
+    """ns_spectra_async reduces the state as it is at that point of the stream, even
+    with steps enqueued before ns_spectra_wait; waiting with nothing in flight is an
+    error.  (The bins are summed with LDS atomics, so two reductions of one state
+    agree to FP64 round-off, not bit for bit.)"""
+    from paper_2603_08892_amd import ns
+    n = 32
+    s = _solver(n, 1.0, prec="fp64", nu=0.01)
+    u = _field(n, 1.0, "sphere", 77, energy=0.5)
+    ud = s.to_device(u)
+    want = s.spectra(ud)
+    s.spectra_async(ud)
+    s.step_ps(ud, 1e-2, 5, "random")
+    got = s.spectra_wait()
+    for key in want:
+        w = np.asarray(want[key])
+        assert np.allclose(got[key], w, rtol=1e-12, atol=1e-14 * np.abs(w).max()), key
+    assert not np.allclose(s.spectra(ud)["totals"][:2], want["totals"][:2], rtol=1e-6)
+    with pytest.raises(ns.NSError) as e:
+        s.spectra_wait()
+    assert e.value.status == ns.NS_ERR_STATE
