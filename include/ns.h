@@ -232,11 +232,14 @@ ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, doub
  * passes of a nonlinear-term evaluation is bracketed by HIP events recorded on
  * the context's stream (this adds a little overhead per launch).  Passes:
  * 0 x-inverse (shift, curl), 1 y-inverse, 2 fused z (c2r, u x omega, r2c),
- * 3 y-forward, 4 x-forward (projection, mask, Runge-Kutta stage).
+ * 3 y-forward, 4 x-forward (projection, mask, Runge-Kutta stage), 5 x-forward
+ * that also runs the next evaluation's x-inverse pass on the stage output it
+ * computes (the step sequences chain their evaluations this way with the
+ * specialised FP32 passes).
  * ns_timing_read waits for the stream, writes per pass the summed event-to-event
  * milliseconds and the number of launches since the previous read (host arrays
  * of NS_NUM_PASSES entries; either may be NULL) and clears the record. */
-#define NS_NUM_PASSES 5
+#define NS_NUM_PASSES 6
 ns_status ns_timing_enable(ns_ctx* ctx, int32_t enable);
 ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches);
 

@@ -309,15 +309,26 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
 }
 
 // ------------------------------------------------------------------ x forward + epilogue
-template <typename C, int OP>
+// FEED (0: none) names the stage output that is the next evaluation's input (1:
+// out0, 2: out1).  The block then also runs that evaluation's x-inverse pass on
+// its own tile (shift sh2): the values just computed are still in registers, at
+// the input positions of the inverse transform (its first radix is the forward
+// transform's last), so the tile is not read back.  An out1 that only feeds the
+// next evaluation is not stored.  FEED needs a.full == 0 (the blocks are then the
+// active tiles, the same as the x-inverse pass).
+template <typename C, int OP, int FEED>
 __global__ void __launch_bounds__(kFastL * C::TPL)
-f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh,
+f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, Shift sh2,
        const int2* __restrict__ tiles, Geom g, EpiArgs<float> a) {
   constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
   using F = RegFft<N, TPL, -1, typename C::Fwd>;
+  using FI = RegFft<N, TPL, +1, typename C::Inv>;
+  static_assert(FEED == 0 || F::RL == FI::R0, "the inverse transform must start with the forward's last radix");
   __shared__ Cx<float> tw[N];
   __shared__ Cx<float> phx[N];
   __shared__ Cx<float> phc[kFastL];
+  __shared__ Cx<float> phx2[FEED ? N : 1];
+  __shared__ Cx<float> phc2[FEED ? kFastL : 1];
   __shared__ Cx<float> xb[N * kFastLp];
   const int tid = threadIdx.x;
   const int l = tid % kFastL, t = tid / kFastL;
@@ -348,7 +359,15 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   constexpr bool need1 = (OP == OP_AVG || OP == OP_HEUN2 || OP == OP_EX1B || OP == OP_EX2B ||
                           OP == OP_RK4_1 || OP == OP_RK4_2 || OP == OP_RK4_3 || OP == OP_ACC ||
                           OP == OP_EULAV);
-  constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2);
+  constexpr bool use1 = (OP == OP_HEUN1 || OP == OP_RK4_0 || OP == OP_RK4_1 || OP == OP_RK4_2) && FEED != 2;
+  static_assert(FEED == 0 || op_can_feed(OP, FEED), "this stage output is not an evaluation input");
+  Cx<float> nx[FEED ? 3 : 1][FEED ? EPT : 1];  // the fed output on this thread's points
+  if constexpr (FEED != 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) nx[c][i] = cx(0.f, 0.f);
+  }
   constexpr int CH = ((need0 && need1) || ((need0 || need1) && N <= 128)) ? EPT / 2 : EPT;
   const LineTest keep = line_test(g, ky, kz);
   const bool line_kept = active && kz < g.kzn;
@@ -376,6 +395,12 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       phase_row(phx, N, sh.s[0], tid, kFastL * TPL);
       phase_cols(phc, ky, kz0, sh, N, tid);
     }
+    if constexpr (FEED != 0) {
+      if (sh2.on) {
+        phase_row(phx2, N, sh2.s[0], tid, kFastL * TPL);
+        phase_cols(phc2, ky, kz0, sh2, N, tid);
+      }
+    }
     const bool col = kz < g.kzn;
     const uint32_t wbase = (uint32_t)(yi * g.kzp + kz0) + l, wstep = (uint32_t)(N * g.kzp);
     // field f + 1 is loaded while field f is transformed
@@ -394,8 +419,10 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
     }
     if (sh.on) phyz = phc[l];
   }
-  if (kz >= g.h || (!a.full && kz >= g.kzn)) return;
+  const bool epi_on = !(kz >= g.h || (!a.full && kz >= g.kzn));
+  if (FEED == 0 && !epi_on) return;
   const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
+  if (epi_on) {
 #pragma unroll
   for (int c0 = 0; c0 < EPT; c0 += CH) {
   if (c0 > 0 || !active) load_ops(c0);
@@ -442,45 +469,98 @@ f_xfwd(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       Cx<float> s0 = cx(0.f, 0.f), s1 = cx(0.f, 0.f);
       if constexpr (need0) s0 = s0v[c][j];
       if constexpr (need1) s1 = s1v[c][j];
+      Cx<float> v0 = cx(0.f, 0.f), v1 = cx(0.f, 0.f);
       if (OP == OP_STORE) {
-        st_off(out0, io0, Nv);
+        v0 = Nv;
       } else if (OP == OP_AVG) {
-        st_off(out0, io0, scale(s1 + Nv, 0.5f));
+        v0 = scale(s1 + Nv, 0.5f);
       } else if (OP == OP_HEUN1) {
         Cx<float> O = cx(0.f, 0.f);
         if (a.force != nullptr && k2 >= 4 && k2 <= 9) O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
-        st_off(out1, io1, scale(s0 + scale(Nv + O, dt), edt));
-        st_off(out0, io0, scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh));
+        v1 = scale(s0 + scale(Nv + O, dt), edt);
+        v0 = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
       } else if (OP == OP_HEUN2) {
-        st_off(out0, io0, s1 + scale(Nv, 0.5f * dt * eh));
+        v0 = s1 + scale(Nv, 0.5f * dt * eh);
       } else if (OP == OP_EX1B) {
-        st_off(out0, io0, scale(s0 + scale(s1 + Nv, 0.5f * dt * a.w), eh));
+        v0 = scale(s0 + scale(s1 + Nv, 0.5f * dt * a.w), eh);
       } else if (OP == OP_EX2B) {
-        st_off(out0, io0, scale(s0, edt) + scale(s1 + Nv, dt * a.w * eh));
+        v0 = scale(s0, edt) + scale(s1 + Nv, dt * a.w * eh);
       } else if (OP == OP_RK4_0) {
-        st_off(out1, io1, scale(s0 + scale(Nv, 0.5f * dt), eh));
-        st_off(out0, io0, scale(s0 + scale(Nv, dt / 6.f), edt));
+        v1 = scale(s0 + scale(Nv, 0.5f * dt), eh);
+        v0 = scale(s0 + scale(Nv, dt / 6.f), edt);
       } else if (OP == OP_RK4_1) {
-        st_off(out1, io1, scale(s0, eh) + scale(Nv, 0.5f * dt));
-        st_off(out0, io0, s1 + scale(Nv, dt / 3.f * eh));
+        v1 = scale(s0, eh) + scale(Nv, 0.5f * dt);
+        v0 = s1 + scale(Nv, dt / 3.f * eh);
       } else if (OP == OP_RK4_2) {
-        st_off(out1, io1, scale(s0, edt) + scale(Nv, dt * eh));
-        st_off(out0, io0, s1 + scale(Nv, dt / 3.f * eh));
+        v1 = scale(s0, edt) + scale(Nv, dt * eh);
+        v0 = s1 + scale(Nv, dt / 3.f * eh);
       } else if (OP == OP_RK4_3) {
-        st_off(out0, io0, s1 + scale(Nv, dt / 6.f));
+        v0 = s1 + scale(Nv, dt / 6.f);
       } else if (OP == OP_ACC) {
-        st_off(out0, io0, s1 + Nv);
+        v0 = s1 + Nv;
       } else if (OP == OP_MID1) {
-        st_off(out0, io0, scale(s0 + scale(Nv, 0.5f * dt), eh));
+        v0 = scale(s0 + scale(Nv, 0.5f * dt), eh);
       } else if (OP == OP_MID2) {
-        st_off(out0, io0, scale(s0, edt) + scale(Nv, dt * eh));
+        v0 = scale(s0, edt) + scale(Nv, dt * eh);
       } else if (OP == OP_EUL) {
-        st_off(out0, io0, scale(s0 + scale(Nv, dt), edt));
+        v0 = scale(s0 + scale(Nv, dt), edt);
       } else {  // OP_EULAV
-        st_off(out0, io0, scale(s0 + scale(s1 + Nv, dt * a.w), edt));
+        v0 = scale(s0 + scale(s1 + Nv, dt * a.w), edt);
       }
+      if constexpr (use1) st_off(out1, io1, v1);
+      st_off(out0, io0, v0);
+      if constexpr (FEED == 1) nx[c][i] = v0;
+      if constexpr (FEED == 2) nx[c][i] = v1;
     }
   }
+  }
+  }
+  if constexpr (FEED != 0) {
+    // the next evaluation's x-inverse pass on this tile (as f_xinv, from registers)
+    const bool col = kz < g.kzn;
+    Cx<float> ux[EPT], uy[EPT], uz[EPT], dy[EPT], dz[EPT];
+    const Cx<float> phyz2 = sh2.on ? phc2[l] : cx(1.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = FI::in_pos(t, i);
+      ux[i] = nx[0][i];
+      uy[i] = nx[1][i];
+      uz[i] = nx[2][i];
+      if (sh2.on) {
+        const Cx<float> phi = cmul(phx2[p], phyz2);
+        ux[i] = cmul(ux[i], phi);
+        uy[i] = cmul(uy[i], phi);
+        uz[i] = cmul(uz[i], phi);
+      }
+      const float kxf = float(kval(p, N));
+      dy[i] = mul_i(scale(uy[i], kxf));
+      dz[i] = mul_i(scale(uz[i], kxf));
+    }
+    const float kyf = float(ky), kzf = float(kz);
+    const uint32_t obase = (uint32_t)(yi * g.kzp + kz0) + l, ostep = (uint32_t)(N * g.kzp);
+    auto store = [&](int f, const Cx<float>* v) {
+      if (col) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) st_off(W + f * g.wcomp, (uint32_t)FI::out_pos(t, i) * ostep + obase, v[i]);
+      }
+    };
+    FI::run(uy, t, lv, tw);
+    store(1, uy);
+    FI::run(uz, t, lv, tw);
+    store(2, uz);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) uy[i] = mul_i(scale(uz[i], kyf) - scale(uy[i], kzf));  // omega_x
+    store(3, uy);
+    FI::run(ux, t, lv, tw);
+    store(0, ux);
+    FI::run(dz, t, lv, tw);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) dz[i] = mul_i(scale(ux[i], kzf)) - dz[i];  // omega_y
+    store(4, dz);
+    FI::run(dy, t, lv, tw);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) dy[i] = dy[i] - mul_i(scale(ux[i], kyf));  // omega_z
+    store(5, dy);
   }
 }
 

@@ -352,9 +352,23 @@ hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, const ns::Shift& sh, const E
   return hipGetLastError();
 }
 
+// Chaining of consecutive evaluations.  In: front_done = this evaluation's
+// x-inverse pass already ran (fused into the previous x-forward pass); feed = the
+// stage output that is the next evaluation's input (0 none, 1 out0, 2 out1) and
+// next_s its shift.  Out: fused = the next evaluation's x-inverse pass ran here
+// (only the specialised passes fuse, and only into a stage that is not in full
+// mode); an out1 that feeds is then not stored.
+struct Chain {
+  bool front_done = false;
+  int feed = 0;
+  const double* next_s = nullptr;
+  bool fused = false;
+};
+
 // Specialised FP32 passes for one compile-time size (same semantics and layout).
-template <typename C, int OP>
-ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift& sh, const EpiArgs<float>& a) {
+template <typename C, int OP, int FEED>
+ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift& sh, const EpiArgs<float>& a,
+                    bool front, const ns::Shift& sh2) {
   const Layout& l = c->lay;
   const Geom& g = l.g;
   Ptrs<float> p = ptrs<float>(c);
@@ -362,10 +376,12 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift
   hipError_t e;
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
-    if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
-                       c->stream, in, lin, p.W, p.tw, sh, p.tiles, g);
-    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+    if (front) {
+      if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
+      hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
+                         c->stream, in, lin, p.W, p.tw, sh, p.tiles, g);
+      if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
+    }
     if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
                        c->stream, p.W, p.tw, l.ntz, g);
@@ -380,19 +396,40 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift
     if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   }
   const int nblk = a.full ? N * l.ntzf : ntiles;
-  if ((e = tstart(c, 4)) != hipSuccess) return hip_check(c, e, "timing event");
+  if ((e = tstart(c, FEED ? 5 : 4)) != hipSuccess) return hip_check(c, e, "timing event");
   if (nblk > 0)
-    hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
-                       c->stream, p.W, p.tw, sh, p.tiles, g, a);
+    hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP, FEED>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
+                       c->stream, p.W, p.tw, sh, sh2, p.tiles, g, a);
   if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   return hip_check(c, hipGetLastError(), "nonlinear-term launch");
+}
+
+template <typename C, int OP>
+ns_status eval_fast_chain(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift& sh,
+                          const EpiArgs<float>& a, Chain* ch) {
+  const bool front = !(ch && ch->front_done);
+  const int feed = (ch && !a.full && c->lay.ntiles_active > 0) ? ch->feed : 0;
+  if (ch) ch->fused = false;
+  if constexpr (ns::op_can_feed(OP, 1)) {
+    if (feed == 1) {
+      ch->fused = true;
+      return eval_fast<C, OP, 1>(c, in, lin, sh, a, front, make_shift(ch->next_s));
+    }
+  }
+  if constexpr (ns::op_can_feed(OP, 2)) {
+    if (feed == 2) {
+      ch->fused = true;
+      return eval_fast<C, OP, 2>(c, in, lin, sh, a, front, make_shift(ch->next_s));
+    }
+  }
+  return eval_fast<C, OP, 0>(c, in, lin, sh, a, front, sh);
 }
 
 // One evaluation of the nonlinear term on `in` (layout lin) with the shift s (NULL
 // or all zero = unshifted); the x-forward epilogue applies OP with the operands
 // and layouts in a.
 template <typename R, int OP>
-ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs<R> a) {
+ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs<R> a, Chain* ch = nullptr) {
   const Layout& l = c->lay;
   const Geom& g = l.g;
   Ptrs<R> p = ptrs<R>(c);
@@ -400,13 +437,14 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs
   hipError_t e;
   if constexpr (std::is_same<R, float>::value) {
     switch (c->fast) {
-      case 64: return eval_fast<ns::Fast64, OP>(c, in, lin, sh, a);
-      case 128: return eval_fast<ns::Fast128, OP>(c, in, lin, sh, a);
-      case 192: return eval_fast<ns::Fast192, OP>(c, in, lin, sh, a);
-      case 256: return eval_fast<ns::Fast256, OP>(c, in, lin, sh, a);
+      case 64: return eval_fast_chain<ns::Fast64, OP>(c, in, lin, sh, a, ch);
+      case 128: return eval_fast_chain<ns::Fast128, OP>(c, in, lin, sh, a, ch);
+      case 192: return eval_fast_chain<ns::Fast192, OP>(c, in, lin, sh, a, ch);
+      case 256: return eval_fast_chain<ns::Fast256, OP>(c, in, lin, sh, a, ch);
       default: break;
     }
   }
+  if (ch) ch->fused = false;  // the size-generic passes run every x-inverse pass on its own
   const size_t lds = lds_strided(l);
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
@@ -497,7 +535,10 @@ ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
   // Between the steps of one call the state stays in scratch fields 6..8 (compact
   // rows, retained modes only; the forward passes use fields 0..5): the first step
   // reads the caller's array, the last writes it back whole.
+  // Each x-forward pass also runs the next evaluation's x-inverse pass on the stage
+  // state it computes (Chain), except after the last step.
   Cx<R>* xs = p.W + 6 * c->lay.g.wcomp;
+  bool fused = false;
   for (int i = 0; i < nsteps; ++i) {
     const bool first = (i == 0), last = (i == nsteps - 1);
     Cx<R>* x = first ? s0 : xs;
@@ -509,15 +550,23 @@ ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
     a.in1 = p.ab;
     a.out0 = p.ab;
     a.out1 = p.sb;
-    if ((st = eval<R, ns::OP_RK4_0>(c, x, lx, nullptr, a)) != NS_OK) return st;
-    if ((st = eval<R, ns::OP_RK4_1>(c, p.sb, K, nullptr, a)) != NS_OK) return st;
-    if ((st = eval<R, ns::OP_RK4_2>(c, p.sb, K, nullptr, a)) != NS_OK) return st;
+    Chain ch;
+    ch.feed = 2;
+    ch.front_done = fused;
+    if ((st = eval<R, ns::OP_RK4_0>(c, x, lx, nullptr, a, &ch)) != NS_OK) return st;
+    ch.front_done = ch.fused;
+    if ((st = eval<R, ns::OP_RK4_1>(c, p.sb, K, nullptr, a, &ch)) != NS_OK) return st;
+    ch.front_done = ch.fused;
+    if ((st = eval<R, ns::OP_RK4_2>(c, p.sb, K, nullptr, a, &ch)) != NS_OK) return st;
     EpiArgs<R> f = epi<R>(c, last ? 1 : 0);
     f.dt = R(dt);
     f.in1 = p.ab;
     f.out0 = last ? s0 : xs;
     f.lo0 = last ? U : K;
-    if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, K, nullptr, f)) != NS_OK) return st;
+    ch.front_done = ch.fused;
+    ch.feed = last ? 0 : 1;
+    if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, K, nullptr, f, &ch)) != NS_OK) return st;
+    fused = ch.fused;
   }
   return NS_OK;
 }
@@ -547,6 +596,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
   // rows, retained modes only; the forward passes use fields 0..5): the first step
   // reads the caller's array (x), the last writes it back whole (y).
   Cx<R>* xs = p.W + 6 * c->lay.g.wcomp;
+  bool fused = false;  // the next evaluation's x-inverse pass already ran
   for (int i = 0; i < nsteps; ++i) {
     const bool first = (i == 0), last = (i == nsteps - 1);
     Cx<R>* x = first ? s0 : xs;
@@ -603,7 +653,11 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
         const ns::Lay lz = stage == 0 ? lx : K;
         EpiArgs<R> a = epi<R>(c, 0);
         a.out0 = p.ab;
-        if ((st = eval<R, ns::OP_STORE>(c, z, lz, sh[0], a)) != NS_OK) return st;
+        // the first evaluation of a stage may already have its x-inverse pass, run by
+        // the x-forward pass that computed its state
+        Chain c0;
+        c0.front_done = fused;
+        if ((st = eval<R, ns::OP_STORE>(c, z, lz, sh[0], a, &c0)) != NS_OK) return st;
         a.in1 = p.ab;
         for (int j = 1; j < ns - 1; ++j)
           if ((st = eval<R, ns::OP_ACC>(c, z, lz, sh[j], a)) != NS_OK) return st;
@@ -613,21 +667,29 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
         f.in0 = x;
         f.li0 = lx;
         f.in1 = p.ab;
+        Chain ch;
+        ch.feed = (stage == 0 || !last) ? 1 : 0;
+        ch.next_s = sh[0];
         if (stage == 0) {
           f.out0 = p.sb;
-          if ((st = eval<R, ns::OP_EX1B>(c, z, lz, sh[ns - 1], f)) != NS_OK) return st;
+          if ((st = eval<R, ns::OP_EX1B>(c, z, lz, sh[ns - 1], f, &ch)) != NS_OK) return st;
         } else {
           f.out0 = y;
           f.lo0 = ly;
-          if ((st = eval<R, ns::OP_EX2B>(c, z, lz, sh[ns - 1], f)) != NS_OK) return st;
+          if ((st = eval<R, ns::OP_EX2B>(c, z, lz, sh[ns - 1], f, &ch)) != NS_OK) return st;
         }
+        fused = ch.fused;
       }
       continue;
     }
-    double al[3] = {0, 0, 0};
+    // Heun: the first-stage shifts of this step and of the next (the x-forward pass
+    // of the second stage runs the next step's first x-inverse pass)
+    double al[3] = {0, 0, 0}, an[3] = {0, 0, 0};
     if (variant == NS_PS_RANDOM) {
-      for (int j = 0; j < 3; ++j)
+      for (int j = 0; j < 3; ++j) {
         al[j] = alphas ? alphas[3 * i + j] : sm64_uniform_host(c->cfg.seed, step0 + i, j);
+        if (!last) an[j] = alphas ? alphas[3 * (i + 1) + j] : sm64_uniform_host(c->cfg.seed, step0 + i + 1, j);
+      }
     }
     double be[3];
     for (int j = 0; j < 3; ++j) be[j] = std::fmod(al[j] + 0.5, 1.0);
@@ -644,13 +706,21 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
       if ((st = hip_check(c, hipGetLastError(), "k_forcing launch")) != NS_OK) return st;
       a.force = p.force;
     }
-    if ((st = eval<R, ns::OP_HEUN1>(c, x, lx, al, a)) != NS_OK) return st;
+    Chain ch;
+    ch.front_done = fused;
+    ch.feed = 2;
+    ch.next_s = be;
+    if ((st = eval<R, ns::OP_HEUN1>(c, x, lx, al, a, &ch)) != NS_OK) return st;
     EpiArgs<R> f = epi<R>(c, fy);
     f.dt = R(dt);
     f.in1 = p.ab;
     f.out0 = y;
     f.lo0 = ly;
-    if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f)) != NS_OK) return st;
+    ch.front_done = ch.fused;
+    ch.feed = last ? 0 : 1;
+    ch.next_s = an;
+    if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f, &ch)) != NS_OK) return st;
+    fused = ch.fused;
   }
   return NS_OK;
 }

@@ -344,6 +344,14 @@ __host__ __device__ constexpr bool op_uses_etab(int op) {
   return op != OP_STORE && op != OP_AVG && op != OP_ACC;
 }
 
+// Stage outputs that are the next evaluation's input in the step sequences (feed
+// 1: out0, 2: out1), for which the x-forward pass can also run that evaluation's
+// x-inverse pass.
+__host__ __device__ constexpr bool op_can_feed(int op, int feed) {
+  return (feed == 2 && (op == OP_HEUN1 || op == OP_RK4_0 || op == OP_RK4_1 || op == OP_RK4_2)) ||
+         (feed == 1 && (op == OP_HEUN2 || op == OP_RK4_3 || op == OP_EX1B || op == OP_EX2B));
+}
+
 template <typename R>
 struct EpiArgs {
   Cx<R>* out0;

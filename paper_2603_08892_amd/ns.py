@@ -32,7 +32,7 @@ ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns
                  "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
                  "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift", "ns_timing_enable",
                  "ns_timing_read", "ns1d_nonlinear", "ns1d_step", "ns_spectra_async", "ns_spectra_wait")
-PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue")
+PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue", "x_forward_inverse")
 
 
 class NSConfig(ctypes.Structure):
