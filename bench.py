@@ -55,23 +55,30 @@ def geometry(n, k2max):
     return {"n": n, "kzn": kzn, "lines": A, "retained": R, "h": n // 2 + 1}
 
 
-def pass_bytes(g, x_forward_extra):
-    """Algorithmic HBM bytes per launch of the five passes of one evaluation.
+def pass_bytes(g):
+    """Algorithmic HBM bytes per launch of each pass of the chained PS-RK2 random step.
 
-    x_inverse  reads the 3 retained components, writes 6 fields on the active lines
-    y_inverse  reads the 6 fields on the active lines, writes the full (x, y) planes k_z < kzn
-    z_fused    reads 6 and writes 3 fields on those planes
-    y_forward  reads 3 fields on the planes, writes them on the active lines
-    x_forward  reads 3 fields on the active lines plus the stage operands, writes the stage outputs
+    x_inverse          reads the 3 retained components, writes 6 fields on the active lines
+                       (only the first evaluation of a call runs it on its own)
+    y_inverse          reads the 6 fields on the active lines, writes the full (x, y) planes k_z < kzn
+    z_fused            reads 6 and writes 3 fields on those planes
+    y_forward          reads 3 fields on the planes, writes them on the active lines
+    x_forward_epilogue the last stage of a call: reads 3 fields on the active lines and the
+                       partial update (retained modes), writes the state's whole half spectrum
+    x_forward_inverse  every other stage: reads 3 fields on the active lines and one stage
+                       operand, writes one stage output (retained modes; S1 only feeds the
+                       next evaluation and is not stored), then the next evaluation's 6
+                       fields on the active lines
     """
-    n, A, R, kzn = g["n"], g["lines"], g["retained"], g["kzn"]
+    n, A, R, kzn, h = g["n"], g["lines"], g["retained"], g["kzn"], g["h"]
     planes = n * n * kzn
     return {
         "x_inverse": (3 * R + 6 * A * n) * ELEM,
         "y_inverse": (6 * A * n + 6 * planes) * ELEM,
         "z_fused": (6 * planes + 3 * planes) * ELEM,
         "y_forward": (3 * planes + 3 * A * n) * ELEM,
-        "x_forward_epilogue": (3 * A * n) * ELEM + x_forward_extra,
+        "x_forward_epilogue": (3 * A * n + 3 * R + 3 * n * n * h) * ELEM,
+        "x_forward_inverse": (9 * A * n + 6 * R) * ELEM,
     }
 
 
@@ -219,16 +226,7 @@ def main():
     n, ct = grids[head]
     _, passes, _ = run_scheme(torch, ns, inputs, head, n, ct, K, W, timing=True)
     g = geometry(n, 4095)
-    R = g["retained"]
-    # x-forward epilogue operands of the Heun stages: stage 1 reads S0 and writes S1 and the
-    # partial update on the active rows; stage 2 reads the partial update and writes the state,
-    # on the retained modes between the steps of one call and over the whole half spectrum
-    # (the caller's array) at the last step of a call, one step in SPEC_EVERY.
-    act = 3 * g["lines"] * n * ELEM
-    full = 3 * n * n * g["h"] * ELEM
-    state_out = (full + (SPEC_EVERY - 1) * 3 * R * ELEM) / SPEC_EVERY
-    xf_extra = ((3 * R * ELEM + 2 * act) + (3 * R * ELEM + state_out)) / 2
-    pb = pass_bytes(g, xf_extra)
+    pb = pass_bytes(g)
     per = {}
     for pname, (tot_ms, cnt) in passes.items():
         if cnt:
