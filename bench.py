@@ -16,8 +16,9 @@ Mgridpts*RKsteps/s (N^3 steps / s / 1e6); the other schemes and the matched-k_ma
 speedups are in `schemes` and `speedup`.  `roofline` is the dominant pass of the
 PS-RK2 random step: algorithmic bytes per launch over its average launch time,
 from HIP events recorded on the library's stream during a second timed run of
-the same steps.  `cpu_baseline` times the FP64 oracle on a few steps of the same
-workload on the host cores.
+the same steps.  `adjoint` times the gradient workload (50 PS-RK2 steps on 128^3,
+checkpoint every 10, hand-written step adjoints).  `cpu_baseline` times the FP64
+oracle on a few steps of the same workload on the host cores.
 """
 
 import argparse
@@ -158,6 +159,44 @@ def run_scheme(torch, ns, inputs, name, n, ct, steps, warmup, timing=False):
     return ms, passes, float(E)
 
 
+def adjoint_run(torch, ns, inputs, reps=3):
+    """The adjoint workload: gradient of the final kinetic energy after 50 PS-RK2 random
+    steps on 128^3 (Taylor-Green plus a 1e-2 seeded perturbation), checkpoint every 10
+    steps (forward with checkpoints, then per segment the recomputed states and the step
+    adjoints in reverse).  Median wall time of `reps` gradients after one warm-up."""
+    from paper_2603_08892_amd.autograd import PSRK2Function, final_energy
+    n, steps, every = NP, 50, 10
+    s = ns.Solver(n, NU, 1.0, precision="fp32", seed=5)
+    u0 = s.to_device(inputs.tg_perturbed(n, 3, ns.retained_bound(n, 1.0)))
+    al = inputs.random_shifts(11, steps)
+
+    def forward():
+        with torch.no_grad():
+            return PSRK2Function.apply(u0, s, DT, steps, "random", al, every)
+
+    def gradient():
+        x = u0.clone().requires_grad_(True)
+        final_energy(PSRK2Function.apply(x, s, DT, steps, "random", al, every)).backward()
+        return x.grad
+
+    def timed(f):
+        out = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(out))
+
+    gradient()
+    fwd, grad = timed(forward), timed(gradient)
+    return {"workload": "adjoint_128: d(final kinetic energy)/d(u0) after 50 PS-RK2 random steps on 128^3 "
+                        "Taylor-Green + 1e-2 perturbation, checkpoint every 10 steps",
+            "ms_per_gradient": round(grad, 3), "ms_forward_only": round(fwd, 3),
+            "gradient_over_forward": round(grad / fwd, 2)}
+
+
 def cpu_baseline(budget_s=20.0):
     """The FP64 oracle on the same Taylor-Green state, PS-RK2 random on 128^3: a bounded
     sample of steps (stops once `budget_s` of host time is used)."""
@@ -187,6 +226,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the timing of the adjoint workload")
     ap.add_argument("--schemes", default="random,approx,exact,rk4")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run 3 elementwise copies of this many MiB (counter calibration)")
@@ -263,6 +303,8 @@ def main():
         "speedup": speed,
         "roofline": roof,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_run(torch, ns, inputs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

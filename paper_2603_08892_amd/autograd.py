@@ -37,10 +37,10 @@ class PSRK2Function(torch.autograd.Function):
         al = None if alphas is None else np.asarray(alphas, dtype=np.float64).reshape(nsteps, 3)
         u = u0.detach().clone().contiguous()
         ckpts = []
-        for i in range(nsteps):
-            if i % checkpoint_every == 0:
-                ckpts.append(u.clone())
-            solver.step_ps(u, dt, 1, variant, alphas=None if al is None else al[i:i + 1])
+        for i in range(0, nsteps, checkpoint_every):
+            ckpts.append(u.clone())
+            k = min(checkpoint_every, nsteps - i)  # a segment in one call (same results as k calls)
+            solver.step_ps(u, dt, k, variant, alphas=None if al is None else al[i:i + k])
         ctx.solver, ctx.dt, ctx.nsteps, ctx.variant = solver, dt, nsteps, variant
         ctx.alphas, ctx.every, ctx.ckpts = al, checkpoint_every, ckpts
         return u
