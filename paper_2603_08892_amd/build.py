@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libns.so")
 SOURCES = [os.path.join(CSRC, "ns_host.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("fft_core.hpp", "ns_kernels.hpp", "ns_aux_kernels.hpp", "ns_adjoint.hpp", "fft_reg.hpp", "ns_fast.hpp")] + [
+HEADERS = [os.path.join(CSRC, f) for f in ("fft_core.hpp", "ns_kernels.hpp", "ns_aux_kernels.hpp", "ns_adjoint.hpp", "fft_reg.hpp", "ns_fast.hpp", "ns_fast_adjoint.hpp", "ns_model1d.hpp")] + [
     os.path.join(ROOT, "include", "ns.h")]
 
 

@@ -18,6 +18,7 @@
 #include "../../include/ns.h"
 #include "ns_adjoint.hpp"
 #include "ns_fast.hpp"
+#include "ns_fast_adjoint.hpp"
 #include "ns_aux_kernels.hpp"
 #include "ns_model1d.hpp"
 
@@ -725,6 +726,35 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
   return NS_OK;
 }
 
+// Specialised FP32 passes of one transposed evaluation (same semantics and layout).
+template <typename C, int AOP>
+ns_status adj_eval_fast(ns_ctx* c, const Cx<float>* st, ns::Lay lst, const ns::Shift& sh,
+                        const LamArgs<float>& la, AdjArgs<float> aa) {
+  const Layout& l = c->lay;
+  const Geom& g = l.g;
+  Ptrs<float> p = ptrs<float>(c);
+  constexpr int N = C::N, P = C::PZ;
+  const int ntiles = l.ntiles_active;
+  if (ntiles > 0) {
+    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
+                       c->stream, st, lst, p.W, p.tw, sh, p.tiles, g);
+    hipLaunchKernelGGL(ns::f_xlam<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
+                       c->stream, la, p.W, p.tw, sh, p.tiles, g);
+    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(9 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
+                       c->stream, p.W, p.tw, l.ntz, g);
+    hipLaunchKernelGGL((ns::f_zadj<typename C::Z, P>), dim3(N * N / P), dim3(P * C::Z::TPL), 0, c->stream,
+                       p.W, p.tw, g);
+    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, -1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
+                       c->stream, p.W, p.tw, l.ntz, g);
+  }
+  aa.ntzf = l.ntzf;
+  const int nblk = aa.full ? N * l.ntzf : ntiles;
+  if (nblk > 0)
+    hipLaunchKernelGGL((ns::f_xadj<typename C::XFwd, AOP>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
+                       c->stream, p.W, p.tw, sh, p.tiles, g, aa);
+  return hip_check(c, hipGetLastError(), "adjoint launch");
+}
+
 // One transposed linearised evaluation at state `st` (layout lst) with shift s:
 // lam-pass input from `la`, adjoint stage combination AOP in the last pass.
 template <typename R, int AOP>
@@ -735,6 +765,15 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
   Ptrs<R> p = ptrs<R>(c);
   const ns::Shift sh = make_shift(s);
   hipError_t e;
+  if constexpr (std::is_same<R, float>::value) {
+    switch (c->fast) {
+      case 64: return adj_eval_fast<ns::Fast64, AOP>(c, st, lst, sh, la, aa);
+      case 128: return adj_eval_fast<ns::Fast128, AOP>(c, st, lst, sh, la, aa);
+      case 192: return adj_eval_fast<ns::Fast192, AOP>(c, st, lst, sh, la, aa);
+      case 256: return adj_eval_fast<ns::Fast256, AOP>(c, st, lst, sh, la, aa);
+      default: break;
+    }
+  }
   const size_t lds = lds_strided(l);
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {

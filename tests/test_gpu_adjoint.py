@@ -112,3 +112,50 @@ def test_autograd_checkpointed_gradient(prec):
         fd = (run(u0 + eps * v) - run(u0 - eps * v)) / (2 * eps)
         ad = float((g.conj() * v).real.sum())
         assert abs(fd - ad) <= tol * max(abs(fd), 1e-3 * float(torch.linalg.vector_norm(g))), (seed, fd, ad)
+
+
+@pytest.mark.parametrize("n,ct,mask", [(64, 1.0, "sphere"), (64, 2 / 3, "sphere"), (64, 1.0, "no_multiple_aliases"),
+                                       (128, 1.0, "sphere")])
+@pytest.mark.parametrize("variant", ["approx", "random", "exact"])
+def test_vjp_specialised_passes_match_oracle(n, ct, mask, variant):
+    """The specialised FP32 adjoint passes (N = 64, 128) against the FP64 oracle's adjoint."""
+    from paper_2603_08892_amd import ns
+    if n == 128 and variant == "approx":
+        pytest.skip("one Heun variant at 128^3 is enough (the oracle adjoint takes seconds)")
+    print(f"[vjp fast] n={n} ct={ct:.3f} {mask} {variant}", flush=True)
+    nu, dt = 0.02, 0.01
+    s = ns.Solver(n, nu, ct, mask=mask, precision="fp32", seed=5)
+    m = grid.mask(n, ct, mask)
+    model = onl.NSModel(n, nu, m)
+    k2 = grid.sphere_k2max(n, ct)
+    u0 = _rep(inputs.random_solenoidal(n, 300 + n, k2, energy=0.5) * m, "fp32")
+    lam = _rep(inputs.random_solenoidal(n, 400 + n, k2) * m, "fp32")
+    alpha = (0.31, 0.77, 0.05)
+    ud, ld = s.to_device(u0), s.to_device(lam)
+    s.vjp_ps(ud, ld, dt, variant, alpha=alpha if variant == "random" else None)
+    if variant == "exact":
+        want = schemes.ps_exact_vjp(model, u0, lam, dt)
+    else:
+        want = schemes.ps_heun_vjp(model, u0, lam, dt, alpha if variant == "random" else (0, 0, 0))
+    rel = np.linalg.norm(_host(ld) - want) / np.linalg.norm(want)
+    assert rel < 1e-4, rel
+
+
+@pytest.mark.parametrize("n,ct", [(128, 2 / 3), (192, 2 / 3), (256, 1.0)])
+def test_vjp_specialised_passes_match_generic(n, ct):
+    """Specialised and size-generic adjoint passes agree to FP32 round-off."""
+    from paper_2603_08892_amd import ns
+    print(f"[vjp fast-vs-generic] n={n} ct={ct:.3f}", flush=True)
+    nu, dt = 1 / 1600, 2e-3
+    fast = ns.Solver(n, nu, ct, precision="fp32", seed=5)
+    gen = ns.Solver(n, nu, ct, precision="fp32", seed=5, generic=True)
+    k2 = grid.sphere_k2max(n, ct)
+    u0 = _rep(inputs.random_solenoidal(n, 11, k2, energy=0.5), "fp32")
+    lam = _rep(inputs.random_solenoidal(n, 12, k2), "fp32")
+    for variant in ("approx", "random", "exact"):
+        al = (0.4, 0.15, 0.9) if variant == "random" else None
+        a, b = fast.to_device(lam), gen.to_device(lam)
+        fast.vjp_ps(fast.to_device(u0), a, dt, variant, alpha=al)
+        gen.vjp_ps(gen.to_device(u0), b, dt, variant, alpha=al)
+        ga, gb = _host(a), _host(b)
+        assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) < 1e-5, variant
