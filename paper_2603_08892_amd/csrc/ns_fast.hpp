@@ -10,6 +10,9 @@
 // owned by t.  LDS: the exchange buffer [position][column] (row pitch L + 1 to
 // spread banks) and the twiddle table.
 // Contiguous pass (z): a block holds P lines, thread (p, t) = (tid div TPL, tid mod TPL).
+// In the step sequences the x-forward kernel can also run the next evaluation's
+// x-inverse pass on its tile (template argument FEED), so a chained evaluation is
+// four launches: y-inverse, z, y-forward, x-forward (+ next x-inverse).
 #pragma once
 
 #include "fft_reg.hpp"
