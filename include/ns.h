@@ -203,7 +203,8 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
                                  const ns_forcing* forcing, int64_t step0);
 
 /* FP64 spectra and totals of the state u_hat (and the transfer with n_hat when
- * non-NULL), Sec. "3D flow: Taylor-Green vortices".  Waits for the result.
+ * non-NULL), Sec. "3D flow: Taylor-Green vortices".  Every bin is summed in a
+ * fixed order, so the result is reproducible bit for bit.  Waits for the result.
  * Returns NS_ERR_NONFINITE (outputs still written) if any entry of u_hat or
  * n_hat is NaN or Inf. */
 ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out);

@@ -14,70 +14,101 @@ __device__ __forceinline__ int shell_of(long long k2) {
 // Bin layout of one partial: [0, nsh) E, [nsh, 2nsh) D, [2nsh, 3nsh) T,
 // then 3 x h one-dimensional energies, then totals E, eps, H, T, nonfinite.
 // Pass 1: every wavefront takes whole k_z rows (fixed k_x, k_y) in a grid-stride
-// loop, the lanes along k_z; a row's share of the 1D spectra in k_x and k_y is
-// summed over the wavefront before its one LDS atomic per bin.  The block's bins
-// (FP64, in LDS) go to partials[block].
+// loop, lanes along k_z, and adds into its own FP64 bins in LDS in a fixed order;
+// the block then sums its wavefronts' bins in wavefront order, so the spectra are
+// reproducible bit for bit.  Along a row the shell index does not decrease with
+// k_z, so a segmented shuffle scan leaves each shell's sum over the 64 lanes in
+// the segment's last lane, which adds it to the bin (the tails of one scan have
+// distinct shells); each lane owns its k_z bin; the row total goes to its k_x and
+// k_y bins from lane 0.
 template <typename R>
 __global__ void __launch_bounds__(1024)
 k_spectra(const Cx<R>* __restrict__ u, const Cx<R>* __restrict__ nh, double nu, int n, int h,
           int nsh, long long comp, double* __restrict__ partials) {
-  extern __shared__ double bins[];
+  extern __shared__ double bins_all[];
   const int nb = 3 * nsh + 3 * h + 5;
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) bins[t] = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwb = blockDim.x >> 6;
+  double* bins = bins_all + wave * nb;
+  for (int t = threadIdx.x; t < nwb * nb; t += blockDim.x) bins_all[t] = 0.0;
   __syncthreads();
   double tE = 0, tD = 0, tH = 0, tT = 0;
   unsigned bad = 0;
-  const int lane = threadIdx.x & 63;
   const long long nrows = (long long)n * n;
-  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long row = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < nrows; row += nwaves) {
+  const long long nwaves = (long long)gridDim.x * nwb;
+  for (long long row = (long long)blockIdx.x * nwb + wave; row < nrows; row += nwaves) {
     const int yi = (int)(row % n), xi = (int)(row / n);
     const int kx = kval(xi, n), ky = kval(yi, n);
     double erow = 0.0;
-    for (int kz = lane; kz < h; kz += 64) {
-      const long long idx = row * h + kz;
-      const double w = (kz == 0 || 2 * kz == n) ? 1.0 : 2.0;
-      const Cx<R> a0 = u[idx], a1 = u[comp + idx], a2 = u[2 * comp + idx];
-      double ar[3] = {(double)a0.re, (double)a1.re, (double)a2.re};
-      double ai[3] = {(double)a0.im, (double)a1.im, (double)a2.im};
-      bool fin = true;
-      for (int c = 0; c < 3; ++c) fin = fin && isfinite(ar[c]) && isfinite(ai[c]);
-      double t = 0.0;
-      if (nh != nullptr) {
-        for (int c = 0; c < 3; ++c) {
-          const Cx<R> b = nh[c * comp + idx];
-          fin = fin && isfinite((double)b.re) && isfinite((double)b.im);
-          t += ar[c] * (double)b.re + ai[c] * (double)b.im;
+    for (int kz0 = 0; kz0 < h; kz0 += 64) {
+      const int kz = kz0 + lane;
+      const bool in = kz < h;
+      double e = 0.0, d = 0.0, t = 0.0;
+      int s = 0x7fffffff;  // lanes past the row end: a key above every shell
+      if (in) {
+        const long long idx = row * h + kz;
+        const double w = (kz == 0 || 2 * kz == n) ? 1.0 : 2.0;
+        const Cx<R> a0 = u[idx], a1 = u[comp + idx], a2 = u[2 * comp + idx];
+        const double ar[3] = {(double)a0.re, (double)a1.re, (double)a2.re};
+        const double ai[3] = {(double)a0.im, (double)a1.im, (double)a2.im};
+        bool fin = true;
+        for (int c = 0; c < 3; ++c) fin = fin && isfinite(ar[c]) && isfinite(ai[c]);
+        if (nh != nullptr) {
+          for (int c = 0; c < 3; ++c) {
+            const Cx<R> b = nh[c * comp + idx];
+            fin = fin && isfinite((double)b.re) && isfinite((double)b.im);
+            t += ar[c] * (double)b.re + ai[c] * (double)b.im;
+          }
+          t *= w;
         }
-        t *= w;
+        const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
+        s = shell_of(k2);  // kept for non-finite lanes too, so the keys stay sorted
+        if (!fin) {
+          ++bad;
+          t = 0.0;
+        } else {
+          e = 0.5 * w * (ar[0] * ar[0] + ai[0] * ai[0] + ar[1] * ar[1] + ai[1] * ai[1] +
+                         ar[2] * ar[2] + ai[2] * ai[2]);
+          d = 2.0 * nu * (double)k2 * e;
+          // helicity density: with u = a + i b, Re(conj(u).(i k x u)) = 2 k.(a x b), so
+          // 1/2 w Re(conj(u).omega) = w k.(a x b)
+          const double cxr = ar[1] * ai[2] - ar[2] * ai[1];
+          const double cyr = ar[2] * ai[0] - ar[0] * ai[2];
+          const double czr = ar[0] * ai[1] - ar[1] * ai[0];
+          tH += w * ((double)kx * cxr + (double)ky * cyr + (double)kz * czr);
+          tE += e;
+          tD += d;
+          tT += t;
+          erow += e;
+          bins[3 * nsh + 2 * h + kz] += e;
+        }
       }
-      if (!fin) { ++bad; continue; }
-      const double e = 0.5 * w * (ar[0] * ar[0] + ai[0] * ai[0] + ar[1] * ar[1] + ai[1] * ai[1] +
-                                  ar[2] * ar[2] + ai[2] * ai[2]);
-      if (e == 0.0 && t == 0.0) continue;
-      const long long k2 = (long long)kx * kx + (long long)ky * ky + (long long)kz * kz;
-      const double d = 2.0 * nu * (double)k2 * e;
-      // helicity density: with u = a + i b, Re(conj(u).(i k x u)) = 2 k.(a x b), so
-      // 1/2 w Re(conj(u).omega) = w k.(a x b)
-      const double cxr = ar[1] * ai[2] - ar[2] * ai[1];
-      const double cyr = ar[2] * ai[0] - ar[0] * ai[2];
-      const double czr = ar[0] * ai[1] - ar[1] * ai[0];
-      const double hd = w * ((double)kx * cxr + (double)ky * cyr + (double)kz * czr);
-      const int s = shell_of(k2);
-      atomicAdd(&bins[s], e);
-      atomicAdd(&bins[nsh + s], d);
-      if (nh != nullptr) atomicAdd(&bins[2 * nsh + s], t);
-      atomicAdd(&bins[3 * nsh + 2 * h + kz], e);
-      erow += e;
-      tE += e; tD += d; tH += hd; tT += t;
+      // an iteration whose contributions are all zero changes no shell bin (skipped)
+      if (__ballot(e != 0.0 || d != 0.0 || t != 0.0) == 0) continue;
+      // segmented inclusive scan over the lanes (keys s non-decreasing with the lane)
+      for (int off = 1; off < 64; off <<= 1) {
+        const double eu = __shfl_up(e, off), du = __shfl_up(d, off);
+        const int su = __shfl_up(s, off);
+        double tu = 0.0;
+        if (nh != nullptr) tu = __shfl_up(t, off);
+        if (lane >= off && su == s) {
+          e += eu;
+          d += du;
+          t += tu;
+        }
+      }
+      const int sn = __shfl_down(s, 1);
+      if (in && (lane == 63 || sn != s)) {
+        bins[s] += e;
+        bins[nsh + s] += d;
+        if (nh != nullptr) bins[2 * nsh + s] += t;
+      }
     }
     for (int off = 32; off > 0; off >>= 1) erow += __shfl_down(erow, off);
-    if (lane == 0 && erow != 0.0) {
-      atomicAdd(&bins[3 * nsh + abs(kx)], erow);
-      atomicAdd(&bins[3 * nsh + h + abs(ky)], erow);
+    if (lane == 0) {
+      bins[3 * nsh + abs(kx)] += erow;
+      bins[3 * nsh + h + abs(ky)] += erow;
     }
   }
-  // totals: wave reduction then one LDS atomic per wave
   for (int off = 32; off > 0; off >>= 1) {
     tE += __shfl_down(tE, off);
     tD += __shfl_down(tD, off);
@@ -86,16 +117,20 @@ k_spectra(const Cx<R>* __restrict__ u, const Cx<R>* __restrict__ nh, double nu, 
     bad += __shfl_down(bad, off);
   }
   const int tot = 3 * nsh + 3 * h;
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&bins[tot + 0], tE);
-    atomicAdd(&bins[tot + 1], tD);
-    atomicAdd(&bins[tot + 2], tH);
-    atomicAdd(&bins[tot + 3], tT);
-    atomicAdd(&bins[tot + 4], (double)bad);
+  if (lane == 0) {
+    bins[tot + 0] = tE;
+    bins[tot + 1] = tD;
+    bins[tot + 2] = tH;
+    bins[tot + 3] = tT;
+    bins[tot + 4] = (double)bad;
   }
   __syncthreads();
   double* out = partials + (long long)blockIdx.x * nb;
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) out[t] = bins[t];
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+    double acc = 0.0;
+    for (int w = 0; w < nwb; ++w) acc += bins_all[w * nb + t];
+    out[t] = acc;
+  }
 }
 
 // Pass 2: fixed-order sum over the blocks' partials.  Eight bins per block of 256

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 #include <new>
@@ -34,8 +35,7 @@ namespace {
 constexpr int kEpt = 8;     // points per thread in the strided passes
 constexpr int kEptZ = 16;   // points per thread in the contiguous (z) pass
 constexpr size_t kAlign = 256;
-constexpr int kSpecBlocks = 256;
-constexpr int kSpecThreads = 1024;  // 16 wavefronts per block, one block per CU
+constexpr int kSpecBlocks = 256;  // one block per CU; its wavefronts keep private LDS bins
 
 thread_local std::string g_last_error;
 
@@ -905,10 +905,13 @@ ns_status spectra_enqueue_t(ns_ctx* c, const void* u, const void* nh) {
   if (c->spec_ev == nullptr &&
       (st = hip_check(c, hipEventCreateWithFlags(&c->spec_ev, hipEventDisableTiming), "spectra event")) != NS_OK)
     return st;
-  const size_t lds = (size_t)l.nbins * sizeof(double);
+  // wavefronts per block: up to 16, as many private bin sets as fit in 128 KB of LDS
+  const size_t set = (size_t)l.nbins * sizeof(double);
+  const int nwb = (int)std::max<size_t>(1, std::min<size_t>(16, (size_t)(128 * 1024) / set));
+  const size_t lds = nwb * set;
   hipError_t e = allow_lds(ns::k_spectra<R>, lds);
   if (e != hipSuccess) return hip_check(c, e, "k_spectra attribute");
-  hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(kSpecThreads), lds, c->stream,
+  hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(64 * nwb), lds, c->stream,
                      static_cast<const Cx<R>*>(u), static_cast<const Cx<R>*>(nh), c->cfg.nu, l.g.n,
                      l.g.h, l.nsh, l.g.comp, p.spec);
   hipLaunchKernelGGL(ns::k_spectra_sum, dim3((l.nbins + 7) / 8), dim3(256), 0, c->stream, p.spec,
