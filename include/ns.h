@@ -32,19 +32,21 @@
  * Shifts are in grid-spacing units: s = (sx, sy, sz) means Delta = s*2*pi/N and the
  * phase factor exp(2 pi i k.s / N) (Eqs. shift_operator, shift_operator_3d).
  *
- * Memory and streams: every field pointer is a device pointer, 256-byte aligned,
- * owned by the caller; the library allocates no device memory.  The caller
- * provides one workspace of ns_workspace_bytes() bytes at ns_init; the context
- * borrows it and must not outlive it.  Work is enqueued on cfg.stream (a
- * hipStream_t; NULL = the null stream) and the calls return without waiting,
- * except ns_spectra, which waits for its few-KB result.  A context is not thread
- * safe; calls that overlap on one context race.
+ * Memory and streams: every field pointer of the 3D calls is a device pointer,
+ * 256-byte aligned, owned by the caller; the library allocates no device memory
+ * (only a few KB of pinned host memory per context for the spectra results).
+ * The caller provides one workspace of ns_workspace_bytes() bytes at ns_init;
+ * the context borrows it and must not outlive it.  Work is enqueued on
+ * cfg.stream (a hipStream_t; NULL = the null stream) and the calls return
+ * without waiting, except ns_spectra and ns_spectra_wait, which wait for their
+ * few-KB result, and ns_timing_read.  A context is not thread safe; calls that
+ * overlap on one context race.
  *
  * Errors: every call returns ns_status.  Arguments are checked on the host before
  * any HIP call.  Asynchronous device faults surface at a later call as
  * NS_ERR_HIP.  ns_last_error gives a message for the last failure on a context
- * (or, for ctx == NULL, for the last ns_init/ns_workspace_bytes failure of the
- * calling thread).
+ * (or, for ctx == NULL, for the last failure of a call without a context --
+ * ns_init, ns_workspace_bytes, the 1D model -- on the calling thread).
  */
 #ifndef NS_H_
 #define NS_H_
@@ -63,7 +65,7 @@ typedef enum {
   NS_ERR_ARG = 1,       /* invalid argument (null/misaligned pointer, bad size or value) */
   NS_ERR_SIZE = 2,      /* workspace too small */
   NS_ERR_HIP = 3,       /* a HIP runtime call failed (possibly an earlier async fault) */
-  NS_ERR_STATE = 4,     /* context unusable */
+  NS_ERR_STATE = 4,     /* out of host memory at ns_init, or ns_spectra_wait with nothing in flight */
   NS_ERR_NONFINITE = 5  /* ns_spectra found a NaN or Inf in its input */
 } ns_status;
 
