@@ -21,3 +21,11 @@ def test_error_index_matches_oracle(nt, h, kmax):
 def test_error_index_rejects_mismatched_runs():
     with pytest.raises(ValueError):
         quality.error_index(np.ones((2, 3, 8)), np.ones((3, 3, 8)), 7)
+
+
+def test_kmax108_runs_retain_the_same_modes():
+    """Every run of the k_max = 108 comparison keeps exactly k^2 <= 11663."""
+    from paper_2603_08892_amd import ns, quality
+    for name, (_, n, ct, _, mask) in quality.RUNS108.items():
+        assert ns.retained_bound(n, ct, mask) == 11663, name
+    assert quality.KMAX108 ** 2 <= 11663 < (quality.KMAX108 + 1) ** 2
