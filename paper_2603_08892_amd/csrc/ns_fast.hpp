@@ -9,7 +9,9 @@
 // thread (l, t) = (tid mod L, tid div L) handles column l, points of the line
 // owned by t.  LDS: the exchange buffer [position][column] (row pitch L + 1 to
 // spread banks) and the twiddle table.
-// Contiguous pass (z): a block holds P lines, thread (p, t) = (tid div TPL, tid mod TPL).
+// Contiguous pass (z): a block holds P lines, thread (p, t) = (tid div TPL, tid mod TPL);
+// a line's threads synchronise at wavefront scope when TPL divides 64 and with
+// block barriers otherwise (N = 216, 324).
 // In the step sequences the x-forward kernel can also run the next evaluation's
 // x-inverse pass on its tile (template argument FEED), so a chained evaluation is
 // four launches: y-inverse, z, y-forward, x-forward (+ next x-inverse).
@@ -240,7 +242,9 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   __shared__ Cx<float> sp[P * N];   // spectrum of f_x + i f_y
   const int tid = threadIdx.x;
   const int p = tid / TPL, t = tid % TPL;
-  static_assert(64 % TPL == 0, "the threads of a line stay in one wavefront");
+  // a line's threads within one wavefront synchronise at wavefront scope; a line
+  // that straddles wavefronts (TPL not dividing 64) uses block barriers
+  constexpr bool WV = (64 % TPL == 0);
   const uint32_t line0 = (uint32_t)blockIdx.x * P;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();  // the line transforms below synchronise only within a wavefront
@@ -275,7 +279,7 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
       else v[i] = cx(a.re + bb.im, bb.re - a.im);
     }
     if (q == 0) fetch(2, ra[0], rb[0]);
-    FI::template run<true>(v, t, lv, tw);
+    FI::template run<WV>(v, t, lv, tw);
     if (q < 2) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i) z[q][i] = v[i];
@@ -291,12 +295,12 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) v[i] = cx(fx[i], fy[i]);
-  FF::template run<true>(v, t, lv, tw);
+  FF::template run<WV>(v, t, lv, tw);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) sp[p * N + FF::out_pos(t, i)] = v[i];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) v[i] = cx(fz[i], 0.f);
-  FF::template run<true>(v, t, lv, tw);
+  FF::template run<WV>(v, t, lv, tw);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) xb[p * LP + FF::out_pos(t, i)] = v[i];
@@ -576,5 +580,11 @@ using Fast64 = FastCfg<LP64, LP64, LP64, 16, LP64>;
 using Fast128 = FastCfg<LP128b, LP128b, LP128b, 8, LP128b>;
 using Fast192 = FastCfg<LP192, LP192, LP192, 8, LP192>;
 using Fast256 = FastCfg<LP256b, LP256b, LP256b, 8, LP256b>;
+// 216 = 12 6 3 and 324 = 12 3 3 3 with 12 points per thread (18 and 27 threads per
+// line): the grids of the k_max = 108 comparison
+using LP216 = LinePlan<216, 18, Radices<12, 6, 3>, Radices<3, 6, 12>>;
+using LP324 = LinePlan<324, 27, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
+using Fast216 = FastCfg<LP216, LP216, LP216, 8, LP216>;
+using Fast324 = FastCfg<LP324, LP324, LP324, 8, LP324>;
 
 }  // namespace ns

@@ -88,7 +88,8 @@ f_xlam(LamArgs<float> la, Cx<float>* __restrict__ W, const Cx<float>* __restrict
 }
 
 // ------------------------------------------------------------------ z pass
-// P lines per block, TPL threads per line in one wavefront.  Inverse slices
+// P lines per block, TPL threads per line (block barriers when a line straddles
+// wavefronts).  Inverse slices
 // (u_x + i u_y), (u_z + i w_x), (w_y + i w_z), (l_x + i l_y), (l_z + i 0) from the
 // half spectra of fields 0..8; the products g1 = omega x lt and g2 = lt x u stay
 // in registers; forward slices (g1x + i g1y), (g1z + i g2x), (g2y + i g2z), each
@@ -100,7 +101,7 @@ f_zadj(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   using FI = RegFft<N, TPL, +1, typename C::Inv>;
   using FF = RegFft<N, TPL, -1, typename C::Fwd>;
   static_assert(FI::RL == FF::R0, "the forward transform must start with the last inverse radix");
-  static_assert(64 % TPL == 0, "the threads of a line stay in one wavefront");
+  constexpr bool WV = (64 % TPL == 0);  // else a line straddles wavefronts: block barriers
   constexpr int LP = line_pitch(N);
   __shared__ Cx<float> tw[N];
   __shared__ Cx<float> xb[P * LP];  // exchanges
@@ -125,7 +126,7 @@ f_zadj(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
       else if (pos < HN) v[i] = cx(a.re - bb.im, a.im + bb.re);
       else v[i] = cx(a.re + bb.im, bb.re - a.im);
     }
-    FI::template run<true>(v, t, lv, tw);
+    FI::template run<WV>(v, t, lv, tw);
     if (q < 4) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i) z[q][i] = v[i];
@@ -151,11 +152,11 @@ f_zadj(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
       const float im = q == 0 ? g1[1][i] : (q == 1 ? g2[0][i] : g2[2][i]);
       v[i] = cx(re, im);
     }
-    FF::template run<true>(v, t, lv, tw);
-    exchange_barrier<true>();  // the previous slice's split has read sp
+    FF::template run<WV>(v, t, lv, tw);
+    exchange_barrier<WV>();  // the previous slice's split has read sp
 #pragma unroll
     for (int i = 0; i < EPT; ++i) sp[p * N + FF::out_pos(t, i)] = v[i];
-    exchange_barrier<true>();
+    exchange_barrier<WV>();
     for (int k = t; k < g.kzn; k += TPL) {
       const Cx<float> c1 = sp[p * N + k], c2 = sp[p * N + ((N - k) % N)];
       const uint32_t off = lbase + k;

@@ -442,6 +442,8 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs
       case 128: return eval_fast_chain<ns::Fast128, OP>(c, in, lin, sh, a, ch);
       case 192: return eval_fast_chain<ns::Fast192, OP>(c, in, lin, sh, a, ch);
       case 256: return eval_fast_chain<ns::Fast256, OP>(c, in, lin, sh, a, ch);
+      case 216: return eval_fast_chain<ns::Fast216, OP>(c, in, lin, sh, a, ch);
+      case 324: return eval_fast_chain<ns::Fast324, OP>(c, in, lin, sh, a, ch);
       default: break;
     }
   }
@@ -771,6 +773,8 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
       case 128: return adj_eval_fast<ns::Fast128, AOP>(c, st, lst, sh, la, aa);
       case 192: return adj_eval_fast<ns::Fast192, AOP>(c, st, lst, sh, la, aa);
       case 256: return adj_eval_fast<ns::Fast256, AOP>(c, st, lst, sh, la, aa);
+      case 216: return adj_eval_fast<ns::Fast216, AOP>(c, st, lst, sh, la, aa);
+      case 324: return adj_eval_fast<ns::Fast324, AOP>(c, st, lst, sh, la, aa);
       default: break;
     }
   }
@@ -983,7 +987,8 @@ ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx
   }
   c->ws = static_cast<char*>(workspace);
   if (cfg->precision == NS_FP32 && c->lay.g.L == ns::kFastL &&
-      (cfg->n == 64 || cfg->n == 128 || cfg->n == 192 || cfg->n == 256) && !(cfg->flags & NS_CFG_GENERIC_PASSES))
+      (cfg->n == 64 || cfg->n == 128 || cfg->n == 192 || cfg->n == 256 || cfg->n == 216 || cfg->n == 324) &&
+      !(cfg->flags & NS_CFG_GENERIC_PASSES))
     c->fast = cfg->n;
   // twiddles W_N^t = exp(-2 pi i t/N), long double, rounded once
   const int n = cfg->n;
