@@ -132,6 +132,14 @@ const char* validate(const ns_config* c) {
   return nullptr;
 }
 
+// Sizes with specialised FP32 passes (ns_fast.hpp), unless the config asks for the
+// size-generic ones.
+bool fast_size(const ns_config* c) {
+  const int n = c->n;
+  return c->precision == NS_FP32 && !(c->flags & NS_CFG_GENERIC_PASSES) &&
+         (n == 64 || n == 128 || n == 192 || n == 216 || n == 256 || n == 324);
+}
+
 bool make_layout(const ns_config* c, Layout* lay) {
   std::vector<int> rad;
   factor_ok(c->n, &rad);
@@ -157,7 +165,9 @@ bool make_layout(const ns_config* c, Layout* lay) {
   for (;;) {
     tx = (n * L + kEpt - 1) / kEpt;
     tx = (tx + 63) / 64 * 64;
-    if (tx <= 512 || L == 1) break;
+    // the specialised passes always tile 16 columns (the generic kernels, which
+    // would need more than 512 threads for that at N > 256, are not used then)
+    if (tx <= 512 || L == 1 || fast_size(c)) break;
     L /= 2;
   }
   g.L = L;
@@ -986,10 +996,7 @@ ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx
     return fail(nullptr, NS_ERR_SIZE, msg);
   }
   c->ws = static_cast<char*>(workspace);
-  if (cfg->precision == NS_FP32 && c->lay.g.L == ns::kFastL &&
-      (cfg->n == 64 || cfg->n == 128 || cfg->n == 192 || cfg->n == 256 || cfg->n == 216 || cfg->n == 324) &&
-      !(cfg->flags & NS_CFG_GENERIC_PASSES))
-    c->fast = cfg->n;
+  if (fast_size(cfg) && c->lay.g.L == ns::kFastL) c->fast = cfg->n;
   // twiddles W_N^t = exp(-2 pi i t/N), long double, rounded once
   const int n = cfg->n;
   const long double pi = 3.141592653589793238462643383279502884L;
