@@ -586,6 +586,9 @@ using LP216 = LinePlan<216, 18, Radices<12, 6, 3>, Radices<3, 6, 12>>;
 using LP324 = LinePlan<324, 27, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
 using Fast216 = FastCfg<LP216, LP216, LP216, 8, LP216>;
 using Fast324 = FastCfg<LP324, LP324, LP324, 8, LP324>;
+// 384 = 12 4 4 2 (inverse), 32 threads per line
+using LP384 = LinePlan<384, 32, Radices<12, 4, 4, 2>, Radices<2, 4, 4, 12>>;
+using Fast384 = FastCfg<LP384, LP384, LP384, 8, LP384>;
 // 512 = 8 8 8 with one wavefront per line (the 2/3-truncated RK4 grid of the
 // 512^3 comparison)
 using LP512 = LinePlan<512, 64, Radices<8, 8, 8>, Radices<8, 8, 8>>;

@@ -137,7 +137,8 @@ const char* validate(const ns_config* c) {
 bool fast_size(const ns_config* c) {
   const int n = c->n;
   return c->precision == NS_FP32 && !(c->flags & NS_CFG_GENERIC_PASSES) &&
-         (n == 64 || n == 128 || n == 192 || n == 216 || n == 256 || n == 324 || n == 512);
+         (n == 64 || n == 128 || n == 192 || n == 216 || n == 256 || n == 324 || n == 384 ||
+          n == 512);
 }
 
 bool make_layout(const ns_config* c, Layout* lay) {
@@ -454,6 +455,7 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs
       case 256: return eval_fast_chain<ns::Fast256, OP>(c, in, lin, sh, a, ch);
       case 216: return eval_fast_chain<ns::Fast216, OP>(c, in, lin, sh, a, ch);
       case 324: return eval_fast_chain<ns::Fast324, OP>(c, in, lin, sh, a, ch);
+      case 384: return eval_fast_chain<ns::Fast384, OP>(c, in, lin, sh, a, ch);
       case 512: return eval_fast_chain<ns::Fast512, OP>(c, in, lin, sh, a, ch);
       default: break;
     }
@@ -786,6 +788,7 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
       case 256: return adj_eval_fast<ns::Fast256, AOP>(c, st, lst, sh, la, aa);
       case 216: return adj_eval_fast<ns::Fast216, AOP>(c, st, lst, sh, la, aa);
       case 324: return adj_eval_fast<ns::Fast324, AOP>(c, st, lst, sh, la, aa);
+      case 384: return adj_eval_fast<ns::Fast384, AOP>(c, st, lst, sh, la, aa);
       case 512: return adj_eval_fast<ns::Fast512, AOP>(c, st, lst, sh, la, aa);
       default: break;
     }

@@ -1,6 +1,6 @@
 """The measured workloads at their full sizes, in the launch configurations the
-benchmark times (the specialised FP32 passes at N = 128, 192, 256; the generic
-passes at N = 360 and 512), against the FP64 oracle or against properties that
+benchmark times (the specialised FP32 passes at N = 128, 192, 256 and 512; the
+generic passes at N = 360), against the FP64 oracle or against properties that
 hold at any size.
 
 - Taylor-Green 128^3 (nu = 1/1600, dt = 2e-3): one step of each phase-shift
