@@ -9,7 +9,7 @@ transforms, shifts, product, projection, truncation and Runge-Kutta update,
 plus the spectra every 10th step), inputs resident in HBM.  As in a time loop,
 the 10 steps between two spectra are one library call.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 3] [--no-cpu-baseline] [--no-hit512]
 
 Prints ONE JSON line.  `value` is the PS-RK2 random throughput on its own grid in
 Mgridpts*RKsteps/s (N^3 steps / s / 1e6); the other schemes and the matched-k_max
@@ -17,7 +17,8 @@ speedups are in `schemes` and `speedup`.  `roofline` is the dominant pass of the
 PS-RK2 random step: algorithmic bytes per launch over its average launch time,
 from HIP events recorded on the library's stream during a second timed run of
 the same steps.  `adjoint` times the gradient workload (50 PS-RK2 steps on 128^3,
-checkpoint every 10, hand-written step adjoints).  `cpu_baseline` times the FP64
+checkpoint every 10, hand-written step adjoints).  `hit_512` times the forced-HIT pairing
+at k_max = 512/3 (RK4 on 512^3 against PS-RK2 random on 384^3).  `cpu_baseline` times the FP64
 oracle on a few steps of the same workload on the host cores.
 """
 
@@ -108,21 +109,24 @@ def committed_traffic(kernel, workload):
     return rec.get("per_launch_bytes", {}).get(f"{workload}:{kernel}")
 
 
-def run_scheme(torch, ns, inputs, name, n, ct, steps, warmup, timing=False):
-    s = ns.Solver(n, NU, ct, precision="fp32", seed=2026)
-    u0 = s.to_device(inputs.taylor_green(n))
+def run_scheme(torch, ns, inputs, name, n, ct, steps, warmup, timing=False, nu=NU, dt=DT, u0=None,
+               forcing=None):
+    """Time `steps` steps of one scheme (after `warmup` untimed ones) from u0 (host array;
+    default the Taylor-Green state); forcing applies to the random scheme."""
+    s = ns.Solver(n, nu, ct, precision="fp32", seed=2026)
+    u0 = s.to_device(inputs.taylor_green(n) if u0 is None else u0)
     u = u0.clone()
 
     def advance(i, k):
         """k steps from step index i in one library call."""
         if name == "rk4":
-            s.step_rk4(u, DT, k)
+            s.step_rk4(u, dt, k)
         elif name == "exact":
-            s.step_ps(u, DT, k, "exact")
+            s.step_ps(u, dt, k, "exact")
         elif name == "approx":
-            s.step_ps(u, DT, k, "approx")
+            s.step_ps(u, dt, k, "approx")
         else:
-            s.step_ps(u, DT, k, "random", step0=i)
+            s.step_ps(u, dt, k, "random", forcing=forcing, step0=i)
 
     def run(nsteps):
         # a time loop: the steps between two spectra in one call each; the host collects
@@ -197,6 +201,34 @@ def adjoint_run(torch, ns, inputs, reps=3):
             "gradient_over_forward": round(grad / fwd, 2)}
 
 
+def hit512_run(torch, ns, inputs, steps, warmup):
+    """The forced-HIT pairing at k_max = 512/3 (K2max = 29127): 2/3-truncated RK4 on 512^3
+    against PS-RK2 random on 384^3 with C_t = 8/9 (the coarser grid with the same retained
+    sphere), from the seeded HIT state E(k) ~ k^4 exp(-2 (k/4)^2), nu from k_max eta = 1 at
+    unit injection, dt = 1e-3.  The PS run carries the stochastic shell forcing; the RK4
+    step of the library has no forcing term, so its run is unforced (the forcing adds a
+    small per-step kernel to the PS side only)."""
+    kmax = 512 / 3
+    nu, dt = kmax ** (-4.0 / 3.0), 1e-3
+    runs = {"rk4_512": ("rk4", 512, 2.0 / 3.0, None), "ps_random_384": ("random", 384, kmax / 192,
+                                                                          {"seed": 13, "injection": 1.0})}
+    out = {}
+    for key, (name, n, ct, fo) in runs.items():
+        k2 = ns.retained_bound(n, ct)
+        u0 = inputs.hit_initial(n, 21, k2)
+        ms, _, _ = run_scheme(torch, ns, inputs, name, n, ct, steps, warmup, nu=nu, dt=dt, u0=u0, forcing=fo)
+        del u0
+        torch.cuda.empty_cache()
+        out[key] = {"n": n, "ct": round(ct, 6), "k2max": k2, "ms_per_step": round(ms / steps, 4),
+                    "mgridpts_steps_per_s": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 1)}
+        print(f"[bench] hit512 {key}: {ms / steps:.3f} ms/step", file=sys.stderr, flush=True)
+    eq = out["rk4_512"]["ms_per_step"] / out["ps_random_384"]["ms_per_step"]
+    out["workload"] = ("forced_hit_kmax_512/3: RK4 on 512^3 C_t=2/3 vs PS-RK2 random on 384^3 C_t=8/9 "
+                       f"(K2max={out['rk4_512']['k2max']}), nu={nu:.4g}, dt={dt}, spectra every 10 steps")
+    out["speedup_ps_random_vs_rk4"] = {"equal_dt": round(eq, 3), "cfl_protocol": round(eq * 0.4 * 512 / 384, 3)}
+    return out
+
+
 def cpu_baseline(budget_s=20.0):
     """The FP64 oracle on the same Taylor-Green state, PS-RK2 random on 128^3: a bounded
     sample of steps (stops once `budget_s` of host time is used)."""
@@ -228,6 +260,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the timing of the adjoint workload")
     ap.add_argument("--schemes", default="random,approx,exact,rk4")
+    ap.add_argument("--no-hit512", action="store_true",
+                    help="skip the forced-HIT pairing at k_max = 512/3 (RK4 on 512^3, PS-RK2 on 384^3)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run 3 elementwise copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -305,6 +339,8 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_run(torch, ns, inputs)
+    if not args.no_hit512:
+        out["hit_512"] = hit512_run(torch, ns, inputs, K, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -586,12 +586,13 @@ using LP216 = LinePlan<216, 18, Radices<12, 6, 3>, Radices<3, 6, 12>>;
 using LP324 = LinePlan<324, 27, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
 using Fast216 = FastCfg<LP216, LP216, LP216, 8, LP216>;
 using Fast324 = FastCfg<LP324, LP324, LP324, 8, LP324>;
-// 384 = 12 4 4 2 (inverse), 32 threads per line
+// 384 = 12 4 4 2 (inverse), 32 threads per line, four lines per z block
 using LP384 = LinePlan<384, 32, Radices<12, 4, 4, 2>, Radices<2, 4, 4, 12>>;
-using Fast384 = FastCfg<LP384, LP384, LP384, 8, LP384>;
+using Fast384 = FastCfg<LP384, LP384, LP384, 4, LP384>;
 // 512 = 8 8 8 with one wavefront per line (the 2/3-truncated RK4 grid of the
-// 512^3 comparison)
+// 512^3 comparison); four lines per z block: at eight, one 512-thread block of
+// about 130 registers a thread is all a CU holds
 using LP512 = LinePlan<512, 64, Radices<8, 8, 8>, Radices<8, 8, 8>>;
-using Fast512 = FastCfg<LP512, LP512, LP512, 8, LP512>;
+using Fast512 = FastCfg<LP512, LP512, LP512, 4, LP512>;
 
 }  // namespace ns
