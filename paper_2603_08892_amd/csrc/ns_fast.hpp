@@ -592,8 +592,9 @@ using Fast384 = FastCfg<LP384, LP384, LP384, 4, LP384>;
 // 512 (the 2/3-truncated RK4 grid of the 512^3 comparison): y and z passes 8 8 8
 // with one wavefront per line, four lines per z block (at eight, one 512-thread
 // block of about 130 registers a thread is all a CU holds); x passes 16 8 4 with
-// 32 threads per line, so that a 16-column tile is a 512-thread block whose
-// threads may hold the chained x pass's registers without spilling
+// 32 threads per line, so that a 16-column tile is a 512-thread block of up to 256
+// registers a thread (the chained x pass still spills some, but fewer waves per
+// line and more registers measured faster than 1024-thread tiles of 128)
 using LP512 = LinePlan<512, 64, Radices<8, 8, 8>, Radices<8, 8, 8>>;
 using LP512x = LinePlan<512, 32, Radices<16, 8, 4>, Radices<4, 8, 16>>;
 using Fast512 = FastCfg<LP512x, LP512, LP512, 4, LP512x>;
