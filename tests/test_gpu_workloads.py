@@ -11,10 +11,10 @@ hold at any size.
 - Adjoint 128^3: gradient of the final kinetic energy after 50 random-shift
   steps (checkpoint every 10) against central differences on 20 seeded
   directions.
-- 512^3 with 2/3 truncation and 360^3 with C_t = 0.9481 (the same k_max): the
-  Taylor-Green nonlinear term against its closed form, energy conservation,
-  zero divergence and mask support of the nonlinear term of a seeded isotropic
-  field, and the energy budget of one step.
+- 512^3 with 2/3 truncation, 384^3 with C_t = 8/9 and 360^3 with C_t = 0.9481 (the
+  same k_max): the Taylor-Green nonlinear term against its closed form, energy
+  conservation, zero divergence and mask support of the nonlinear term of a
+  seeded isotropic field, and the energy budget of one step.
 
 Tolerances: FP32 states 1e-5 relative L2 and 3e-4 relative to the largest entry
 per step (the stated FP32 field tolerance, as in test_gpu_parity); the
@@ -170,9 +170,10 @@ def test_adjoint_128_fifty_steps():
         assert abs(fd - ad) <= 1e-3 * max(abs(fd), 1e-3 * gn), (seed, fd, ad)
 
 
-@pytest.mark.parametrize("n,ct", [(512, 2 / 3), (360, 0.9481)])
+@pytest.mark.parametrize("n,ct", [(512, 2 / 3), (384, 512 / 3 / 192), (360, 0.9481)])
 def test_large_grids_taylor_green_closed_form(n, ct):
-    """Generic passes (no specialised plan at these sizes); compared on the device."""
+    """512^3 and 384^3 on the specialised passes, 360^3 on the generic ones (no
+    specialised plan at that size); compared on the device."""
     import torch
     print(f"[workload] Taylor-Green closed form {n}^3 C_t={ct:.4f}", flush=True)
     s = _solver(n, ct, NU_TG)
@@ -195,11 +196,13 @@ def test_large_grids_taylor_green_closed_form(n, ct):
     assert err <= 1e-5 / 32, err
 
 
-def test_large_grid_360_properties_and_energy_budget():
-    """Seeded isotropic field on 360^3 with C_t = 0.9481 (k_max of 512^3 at 2/3):
+@pytest.mark.parametrize("n,ct", [(360, 0.9481), (384, 512 / 3 / 192)])
+def test_large_grid_properties_and_energy_budget(n, ct):
+    """Seeded isotropic field on 360^3 (C_t = 0.9481, generic passes) and 384^3 (C_t = 8/9,
+    specialised passes), both at about the k_max of 512^3 at 2/3:
     <u, N> = 0, k.N = 0, N = 0 outside the mask, and one random-shift step changes the
     energy by the dissipation -2 nu sum w k^2 |u|^2 dt to O(dt^2)."""
-    n, ct, nu, dt = 360, 0.9481, 2e-3, 2e-5
+    nu, dt = 2e-3, 2e-5
     print(f"[workload] {n}^3 C_t={ct} properties", flush=True)
     s = _solver(n, ct, nu, seed=9)
     k2max = grid.sphere_k2max(n, ct)
