@@ -14,16 +14,23 @@ grid       wavenumbers, truncation thresholds and masks, Hermitian weights, shel
 transforms forward (1/N per axis) and inverse (unnormalised) real FFTs
 nonlinear  phase shift, curl, projection, u x omega, shift averages, padded product,
            and the transpose of the linearised nonlinear term (for the adjoint)
-schemes    integrating-factor Euler, midpoint RK2, Lawson RK4, phase-shifted RK2
-           (exact / approx / random, optional split forcing) and the step adjoint
-spectra    shell, 1D, dissipation and transfer spectra; totals
-forcing    SplitMix64 counter-based draws, forcing amplitudes and injection scaling
+schemes    integrating-factor Euler, midpoint RK2, Lawson RK4 (optional forcing),
+           phase-shifted RK2 (exact / approx / random, optional split forcing) and the
+           step adjoint
+spectra    shell, 1D, dissipation and transfer spectra; totals; the time-integrated
+           energy budget E - E0 + int eps dt - int P dt
+forcing    SplitMix64 counter-based draws, forcing amplitudes, injection scaling and
+           the energy injected per step
 quality    error index of a run's 1D spectra against a reference run
 nl1d       the 1D quadratic model dS/dt = -S^2
 
 Parity status: every function is pinned by at least one test in
-``tests/test_oracle_*.py`` except the forcing draw itself (parity unpinned against
-the paper, which gives no forcing formula; only its injection rate is pinned).
+``tests/test_oracle_pins.py``: the forcing inside the schemes by the closed-form
+forced solution of a linear model and by self-convergence orders, the transfer
+spectrum by T(u, u) = 2 E(k) and the shell energy balance, the budget by the
+exact-decay closed form and its convergence orders.  The forcing draw itself is
+parity unpinned against the paper, which gives no forcing formula: its shape is
+a reading, and only its injection rate is pinned.
 """
 
 from . import grid, transforms, nonlinear, schemes, spectra, forcing, nl1d  # noqa: F401

@@ -116,3 +116,15 @@ def forcing(uh0, dt, seed, step):
     """The forcing O = a g applied during step `step` from state u_hat0."""
     g = forcing_shape(uh0.shape[-2], seed, step)
     return amplitude(uh0, g, dt) * g
+
+
+def injected(uh0, o, dt):
+    """Energy the forcing O puts into the state over one step of length dt from
+    u_hat0: E(u0 + dt O) - E(u0) = dt sum w Re(conj(u0).O) + dt^2/2 sum w |O|^2.
+    With O from `forcing` it equals dt (unit injection rate); summed over the steps
+    it is the integral of the injected power in the energy budget."""
+    n = uh0.shape[-2]
+    w = grid.hermitian_weight(n)
+    b = float(np.sum(w * np.real(np.conj(uh0) * o)))
+    gg = float(np.sum(w * np.abs(o) ** 2))
+    return dt * b + 0.5 * dt * dt * gg

@@ -20,6 +20,8 @@ Readings (where the paper does not print a formula):
 * Heun / Rogallo: S1 = E_dt (S0 + dt N0); S_new = E_dt S0 + dt/2 E_{dt/2} (N0 + N1)
   (Eq. Rogallo1981 and its 3D form with two shifts alpha, beta).
 * Split forcing (Eq. forcing-eq and the stage formulas after it) with O0 = O1 = O.
+* The RK4 baseline takes the same forcing as an additive term of every stage slope,
+  held constant over the step (the paper forces both schemes; it prints no RK4 form).
 """
 
 import numpy as np
@@ -67,18 +69,24 @@ def ps_exact8(model, s0, dt):
     return rk2(model, s0, dt, shifts=eight)
 
 
-def rk4(model, s0, dt):
-    """Classical RK4 in Lawson form, unshifted (the truncation baseline)."""
+def rk4(model, s0, dt, forcing=None):
+    """Classical RK4 in Lawson form, unshifted (the truncation baseline).
+
+    forcing: an additive term O held constant over the step (drawn at its start, as
+    in the split phase-shift scheme), added to the nonlinear term of every stage:
+    the stage slopes are N_i + O.
+    """
     h = 0.5 * dt
     e = model.E(h)
     z = model.zero
-    n0 = model.nl(s0, z)
+    o = 0.0 if forcing is None else forcing
+    n0 = model.nl(s0, z) + o
     sa = e * (s0 + h * n0)
-    n1 = model.nl(sa, z)
+    n1 = model.nl(sa, z) + o
     sb = e * s0 + h * n1
-    n2 = model.nl(sb, z)
+    n2 = model.nl(sb, z) + o
     sc = e * e * s0 + dt * e * n2
-    n3 = model.nl(sc, z)
+    n3 = model.nl(sc, z) + o
     return e * e * s0 + (dt / 6.0) * (e * e * n0 + 2.0 * e * n1 + 2.0 * e * n2 + n3)
 
 

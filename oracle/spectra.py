@@ -51,6 +51,32 @@ def spectra(uh, nu, nh=None):
             "totals": totals}
 
 
+def budget(e, eps, inj, dt):
+    """Time-integrated energy budget of a run sampled every step (Sec. "3D flow:
+    Taylor-Green vortices": dE/dt = -eps for the decaying flow; Sec. "Numerical
+    methods": the forced runs inject energy at a given rate).
+
+    e, eps: E and eps at t_j = j dt, j = 0..M; inj: energy injected by the forcing
+    in each step j -> j + 1 (M values, or None for a free run).  Returns the
+    residuals r_j = E_j - E_0 + int_0^{t_j} eps dt - int_0^{t_j} P dt, j = 0..M,
+    with the dissipation integrated by the trapezoid rule step by step and the
+    injection summed.  Written as an explicit loop.
+    """
+    e = [float(v) for v in e]
+    eps = [float(v) for v in eps]
+    m = len(e) - 1
+    if len(eps) != m + 1 or (inj is not None and len(inj) != m):
+        raise ValueError("need M + 1 samples of E and eps and M injections")
+    out = [0.0]
+    diss, work = 0.0, 0.0
+    for j in range(m):
+        diss += 0.5 * dt * (eps[j] + eps[j + 1])
+        if inj is not None:
+            work += float(inj[j])
+        out.append(e[j + 1] - e[0] + diss - work)
+    return np.array(out)
+
+
 def energy(uh):
     """Total kinetic energy E = (1/2) sum_k w |u_hat|^2."""
     n = uh.shape[-2]

@@ -592,3 +592,167 @@ def test_error_index_closed_forms():
     run[0][0][0] *= 5
     run[0][0][16] *= 5
     assert abs(quality.error_index(run, ref, 15)[0] - want / 3) < 1e-12
+
+
+# ----------------------------------------------------------------------------- forcing in the schemes
+class _LinearModel:
+    """dS/dt = sigma S + O with no nonlinear term: a test double of the scheme model
+    whose forced solution is known in closed form,
+    S(t) = exp(sigma t) S0 + (exp(sigma t) - 1)/sigma O (t O where sigma = 0)."""
+
+    zero = (0.0, 0.0, 0.0)
+    half = (0.5, 0.5, 0.5)
+
+    def __init__(self, n, nu):
+        self.sigma = -nu * grid.k2grid(n).astype(np.float64)
+
+    def nl(self, s, shift):
+        return np.zeros_like(s)
+
+    def E(self, tau):
+        return np.exp(self.sigma * tau)
+
+    def exact(self, s0, o, t):
+        e = np.exp(self.sigma * t)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            phi = np.where(self.sigma != 0, (e - 1) / np.where(self.sigma != 0, self.sigma, 1), t)
+        return e * s0 + phi * o
+
+
+def test_forced_schemes_linear_closed_form():
+    """Eq. forcing-eq: with N = 0 and a constant forcing the Heun split step is the
+    trapezoid-like rule dt E_{dt/2} O for the forced integral (local error dt^3) and
+    Lawson RK4 is Simpson's rule (local error dt^5).  A wrong weight of O in any
+    stage or in the final update leaves an O(dt) error and fails."""
+    n, nu = 16, 0.3
+    lm = _LinearModel(n, nu)
+    u0 = inputs.random_solenoidal(n, 3, grid.sphere_k2max(n, 1.0), energy=0.5)
+    o = forcing.forcing_shape(n, 5, 2)
+    eh, e4 = [], []
+    for dt in (0.1, 0.05, 0.025):
+        want = lm.exact(u0, o, dt)
+        eh.append(np.abs(schemes.ps_heun(lm, u0, dt, (0.2, 0.4, 0.6), forcing=o) - want).max())
+        e4.append(np.abs(schemes.rk4(lm, u0, dt, forcing=o) - want).max())
+    sh = np.log2(np.array(eh[:-1]) / np.array(eh[1:]))
+    s4 = np.log2(np.array(e4[:-1]) / np.array(e4[1:]))
+    assert np.all(np.abs(sh - 3) < 0.15), sh
+    assert np.all(np.abs(s4 - 5) < 0.15), s4
+    assert eh[0] < 1e-3 and e4[0] < 1e-6
+
+
+def test_forced_schemes_self_convergence():
+    """Split forcing with a fixed O on the alias-free product (N = 12): the Heun step
+    converges as dt^2 and forced RK4 as dt^4 (global error at t = 0.5 against 128
+    steps).  Dropping O from the first stage of the Heun step leaves a first-order
+    scheme, so this also fixes where O enters."""
+    n, T = 12, 0.5
+    m = grid.mask(n, 1.0)
+    clean = onl.NSModel(n, 0.02, m, clean=True)
+    u0 = inputs.random_solenoidal(n, 3, grid.sphere_k2max(n, 1.0), energy=0.1)
+    o = 0.1 * forcing.forcing_shape(n, 5, 2)
+
+    def run(step, k):
+        u = u0
+        for _ in range(k):
+            u = step(u, T / k)
+        return u
+
+    for step, order in ((lambda u, dt: schemes.ps_heun(clean, u, dt, (0, 0, 0), forcing=o), 2),
+                        (lambda u, dt: schemes.rk4(clean, u, dt, forcing=o), 4)):
+        ref = run(step, 128)
+        e = [np.abs(run(step, k) - ref).max() for k in (4, 8, 16)]
+        sl = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+        assert np.all(np.abs(sl - order) < 0.35), (order, sl)
+
+
+# ----------------------------------------------------------------------------- transfer spectrum
+def test_transfer_spectrum_identity_and_shell_balance():
+    """T(n) = sum_shell w Re(conj(u).N): with N = u it is twice the shell energy, and
+    over one integrating-factor Euler step E_n(t + dt) - E_n(t) = dt (T(n) - D(n))
+    + O(dt^2) shell by shell (the shell form of dE/dt = T - D, Sec. "3D flow:
+    Taylor-Green vortices")."""
+    n, nu = 16, 0.05
+    m = grid.mask(n, 1.0)
+    model = onl.NSModel(n, nu, m)
+    u = inputs.random_solenoidal(n, 8, grid.sphere_k2max(n, 1.0), energy=0.5)
+    sp = spectra.spectra(u, nu, nh=u)
+    assert np.abs(sp["t_shell"] - 2 * sp["e_shell"]).max() <= 1e-15 * sp["e_shell"].max()
+    assert abs(sp["totals"][3] - 2 * sp["totals"][0]) <= 1e-14 * sp["totals"][0]
+    sp0 = spectra.spectra(u, nu, nh=model.nl(u, model.zero))
+    rate = sp0["t_shell"] - sp0["d_shell"]
+    errs = []
+    for dt in (1e-3, 5e-4):
+        de = (spectra.spectra(schemes.euler(model, u, dt), nu)["e_shell"] - sp0["e_shell"]) / dt
+        errs.append(np.abs(de - rate).max())
+    assert errs[0] < 2e-2 * np.abs(rate).max()
+    assert abs(errs[0] / errs[1] - 2) < 0.1, errs
+    # the transfer of the dealiased term conserves energy
+    assert abs(sp0["totals"][3]) < 1e-14 * np.abs(sp0["t_shell"]).max()
+
+
+# ----------------------------------------------------------------------------- energy budget
+def test_budget_exact_decay_closed_form():
+    """u = (sin 2y, 0, 0) decays as E0 q^j, q = exp(-2 nu k^2 dt), with eps = 2 nu k^2 E.
+    The trapezoid-rule budget r_j = E_j - E_0 + sum dt/2 (eps + eps') is then the
+    geometric sum (q^j - 1) E0 + E0 lambda dt/2 (1 + q)/(1 - q) (1 - q^j), lambda =
+    2 nu k^2, and vanishes as dt^2."""
+    n, nu = 16, 0.05
+    u0 = inputs.shear_wave(n, 2)
+    model = onl.NSModel(n, nu, grid.mask(n, 1.0))
+    lam = 2 * nu * 4
+    last = []
+    for dt in (0.1, 0.05):
+        steps = int(round(1.0 / dt))
+        u, e, eps = u0, [], []
+        for j in range(steps + 1):
+            t = spectra.spectra(u, nu)["totals"]
+            e.append(t[0])
+            eps.append(t[1])
+            if j < steps:
+                u = schemes.ps_heun(model, u, dt, (0.3, 0.1, 0.7))
+        r = spectra.budget(e, eps, None, dt)
+        q = np.exp(-lam * dt)
+        jj = np.arange(steps + 1)
+        closed = (q ** jj - 1) * e[0] + e[0] * lam * dt / 2 * (1 + q) / (1 - q) * (1 - q ** jj)
+        assert np.abs(r - closed).max() < 1e-14
+        last.append(r[-1])
+    assert abs(last[0] / last[1] - 4) < 0.05
+
+
+def test_budget_taylor_green_and_forced_orders():
+    """The dealiased transfer conserves energy, so the free Taylor-Green run (N = 32,
+    PS-RK2 random, t = 0.4) closes its budget to the time error, O(dt^2); the forced
+    run (N = 16, unit injection redrawn every step, injected energy
+    E(u0 + dt O) - E(u0) per step) closes it to O(dt), with the injection summing to
+    the elapsed time."""
+    n, nu, T = 32, 0.02, 0.4
+    model = onl.NSModel(n, nu, grid.mask(n, 1.0))
+    res = []
+    for dt in (0.04, 0.02):
+        steps = int(round(T / dt))
+        u, e, eps = inputs.taylor_green(n), [], []
+        for j in range(steps + 1):
+            t = spectra.spectra(u, nu)["totals"]
+            e.append(t[0])
+            eps.append(t[1])
+            if j < steps:
+                u = schemes.ps_heun(model, u, dt, forcing.random_shift(7, j))
+        res.append(spectra.budget(e, eps, None, dt)[-1])
+    assert abs(res[0]) < 1e-6 and abs(res[0] / res[1] - 4) < 0.3, res
+    n, nu, T = 16, 0.02, 0.2
+    model = onl.NSModel(n, nu, grid.mask(n, 1.0))
+    res = []
+    for dt in (0.02, 0.01):
+        steps = int(round(T / dt))
+        u, e, eps, inj = inputs.hit_initial(n, 3, grid.sphere_k2max(n, 1.0)), [], [], []
+        for j in range(steps + 1):
+            t = spectra.spectra(u, nu)["totals"]
+            e.append(t[0])
+            eps.append(t[1])
+            if j < steps:
+                o = forcing.forcing(u, dt, 9, j)
+                inj.append(forcing.injected(u, o, dt))
+                u = schemes.ps_heun(model, u, dt, forcing.random_shift(7, j), forcing=o)
+        assert abs(sum(inj) - T) < 1e-12
+        res.append(spectra.budget(e, eps, inj, dt)[-1])
+    assert abs(res[0]) < 0.05 * T and abs(res[0] / res[1] - 2) < 0.4, res
