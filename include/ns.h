@@ -39,7 +39,7 @@
  * the context borrows it and must not outlive it.  Work is enqueued on
  * cfg.stream (a hipStream_t; NULL = the null stream) and the calls return
  * without waiting, except ns_spectra and ns_spectra_wait, which wait for their
- * few-KB result, and ns_timing_read.  A context is not thread safe; calls that
+ * few-KB result, ns_budget_read and ns_timing_read.  A context is not thread safe; calls that
  * overlap on one context race.
  *
  * Errors: every call returns ns_status.  Arguments are checked on the host before
@@ -117,12 +117,12 @@ typedef struct {
  * agree to FP32 round-off; meant for testing and comparison. */
 #define NS_CFG_GENERIC_PASSES 1
 
-/* Forcing of the "split" phase-shift scheme (Eq. forcing-eq): a divergence-free
- * random field on the shell k2_lo <= |k|^2 <= k2_hi (only 4..9 supported, the
- * 96 modes of 2 <= |k| <= 3), redrawn every step from SplitMix64(seed, step) and
- * scaled so that the step injects energy at rate `injection`:
- * a sum w Re(conj(u0).g) + a^2 dt/2 sum w |g|^2 = injection, O = a g, and O is
- * added to both stages (O0 = O1 = O). */
+/* Forcing of the "split" phase-shift scheme (Eq. forcing-eq) and of the RK4
+ * baseline: a divergence-free random field on the shell k2_lo <= |k|^2 <= k2_hi
+ * (only 4..9 supported, the 96 modes of 2 <= |k| <= 3), redrawn every step from
+ * SplitMix64(seed, step) and scaled so that the step injects energy at rate
+ * `injection`: a sum w Re(conj(u0).g) + a^2 dt/2 sum w |g|^2 = injection, O = a g.
+ * The Heun schemes add O to both stages (O0 = O1 = O), RK4 to all four slopes. */
 typedef struct {
   int32_t k2_lo, k2_hi;  /* must be 4 and 9 */
   double injection;      /* energy injection rate, > 0 */
@@ -162,7 +162,12 @@ ns_status ns_destroy(ns_ctx* ctx);
 
 const char* ns_last_error(const ns_ctx* ctx);
 
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on.  The context's workspace (scratch
+ * fields, stage buffers, tables, spectra partials, budget) is shared by every
+ * call, so the caller must order the new stream after the work already enqueued
+ * on the old one (an event recorded on the old stream and waited for on the new
+ * one); otherwise a later call can overwrite buffers that earlier work still
+ * reads. */
 ns_status ns_set_stream(ns_ctx* ctx, void* stream);
 
 /* One evaluation of the nonlinear term (Sec. "Aliasing description" for the
@@ -176,10 +181,14 @@ ns_status ns_nonlinear(ns_ctx* ctx, const void* u_hat, void* n_hat, const double
 
 /* nsteps steps of classical RK4 in integrating-factor (Lawson) form, unshifted
  * (the 2/3-truncation baseline of Tables I-V when cfg.ct = 2/3), in place on the
- * state u_hat.  dt > 0, nsteps >= 0.  As for ns_step_rk2_phaseshift, the
+ * state u_hat.  dt > 0, nsteps >= 0.  forcing (nullable): the large-scale forcing
+ * of ns_forcing, drawn for step step0 + s from that step's start state exactly as
+ * in ns_step_rk2_phaseshift, and added to the slope of every stage (N_i + O; the
+ * forced runs of Table V force both schemes).  As for ns_step_rk2_phaseshift, the
  * intermediate states of one call stay in the workspace; nsteps steps in one call
  * are bit-identical to nsteps calls of one step. */
-ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps);
+ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps, const ns_forcing* forcing,
+                            int64_t step0);
 
 /* nsteps steps of phase-shift RK2 (Eqs. Rogallo1981 and its 3D form; split
  * forcing of Eq. forcing-eq when forcing != NULL, Heun variants only), or of
@@ -221,14 +230,39 @@ ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spect
 ns_status ns_spectra_async(ns_ctx* ctx, const void* u_hat, const void* n_hat);
 ns_status ns_spectra_wait(ns_ctx* ctx, ns_spectra_out* out);
 
-/* Transpose of the linearised phase-shift RK2 step at state u_hat0 (no forcing):
+/* Transpose of the linearised phase-shift RK2 step at state u_hat0:
  * lam holds dJ/dS_{n+1} on entry and dJ/dS_n on return, both with respect to the
  * Parseval inner product <a,b> = sum_k w Re(conj(a).b) (w = 1 on the k_z = 0 and
  * N/2 planes, 2 elsewhere); multiply by w for the gradient of the real and
  * imaginary parts taken as independent variables.  alpha: the first-stage shift
- * used by the forward step (NS_PS_RANDOM; NULL for the other variants). */
+ * used by the forward step (NS_PS_RANDOM; NULL for the other variants).
+ * forcing (nullable; Heun variants): the forward step was forced (Eq. forcing-eq)
+ * with the draw of step `step`; it is redrawn from u_hat0, and the adjoint also
+ * carries the dependence of the forcing amplitude on u_hat0 (a B + a^2 dt/2 G =
+ * injection with B = <u_hat0, g>, so da/dB = -a / sqrt(B^2 + 2 dt G injection)). */
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt,
-                                int32_t variant, const double alpha[3]);
+                                int32_t variant, const double alpha[3], const ns_forcing* forcing,
+                                int64_t step);
+
+/* FP64 time-integrated energy budget on the GPU (Sec. "3D flow: Taylor-Green
+ * vortices": dE/dt = -eps for the free flow; Sec. "Numerical methods": the forced
+ * runs inject energy at a given rate).  ns_budget_start enqueues a reduction of
+ * E = 1/2 sum w |u|^2 and eps = nu sum w |k|^2 |u|^2 over the retained modes of
+ * u_hat and starts the record there; while the budget is on, every step of
+ * ns_step_rk4_trunc and ns_step_rk2_phaseshift enqueues the same reduction of the
+ * state after it (summed in a fixed order, so reproducible bit for bit) and
+ * updates the record on the device: t += dt, int eps dt by the trapezoid rule
+ * step by step, int P dt += the energy the step's forcing injects,
+ * dt (a B + a^2 dt/2 G) = E(u0 + dt O) - E(u0).  ns_budget_read waits for the
+ * stream and writes NS_BUDGET_LEN doubles: t, E, eps, E0, int eps dt, int P dt,
+ * P of the last step (0 if unforced), and the residual
+ * E - E0 + int eps dt - int P dt.  ns_budget_stop ends the per-step updates (the
+ * record is kept).  The reductions read the state once per step (3 retained
+ * components), a few percent of a step's traffic. */
+#define NS_BUDGET_LEN 8
+ns_status ns_budget_start(ns_ctx* ctx, const void* u_hat);
+ns_status ns_budget_stop(ns_ctx* ctx);
+ns_status ns_budget_read(ns_ctx* ctx, double* out);
 
 /* Per-pass timing, the GPU counterpart of the per-task time shares of the
  * paper's profiles (Figs. 10 and 14).  While enabled, every launch of the five

@@ -28,10 +28,14 @@ def hermitian_weight(n, device, dtype):
 
 
 class PSRK2Function(torch.autograd.Function):
-    """u_T = PSRK2Function.apply(u0, solver, dt, nsteps, variant, alphas, checkpoint_every)."""
+    """u_T = PSRK2Function.apply(u0, solver, dt, nsteps, variant, alphas, checkpoint_every[, forcing]).
+
+    forcing: None, or dict(seed=..., injection=...) for the split forcing of the Heun
+    variants, step i drawing with key i (the gradient includes the dependence of the
+    forcing amplitude on the state)."""
 
     @staticmethod
-    def forward(ctx, u0, solver, dt, nsteps, variant, alphas, checkpoint_every):
+    def forward(ctx, u0, solver, dt, nsteps, variant, alphas, checkpoint_every, forcing=None):
         if variant == "random" and alphas is None:
             raise ValueError("the random variant needs explicit per-step shifts (alphas [nsteps, 3])")
         al = None if alphas is None else np.asarray(alphas, dtype=np.float64).reshape(nsteps, 3)
@@ -40,8 +44,9 @@ class PSRK2Function(torch.autograd.Function):
         for i in range(0, nsteps, checkpoint_every):
             ckpts.append(u.clone())
             k = min(checkpoint_every, nsteps - i)  # a segment in one call (same results as k calls)
-            solver.step_ps(u, dt, k, variant, alphas=None if al is None else al[i:i + k])
-        ctx.solver, ctx.dt, ctx.nsteps, ctx.variant = solver, dt, nsteps, variant
+            solver.step_ps(u, dt, k, variant, alphas=None if al is None else al[i:i + k], forcing=forcing,
+                           step0=i)
+        ctx.solver, ctx.dt, ctx.nsteps, ctx.variant, ctx.forcing = solver, dt, nsteps, variant, forcing
         ctx.alphas, ctx.every, ctx.ckpts = al, checkpoint_every, ckpts
         return u
 
@@ -58,12 +63,14 @@ class PSRK2Function(torch.autograd.Function):
             states = [ctx.ckpts[seg]]
             u = ctx.ckpts[seg].clone()
             for i in range(start, end - 1):
-                s.step_ps(u, dt, 1, ctx.variant, alphas=None if al is None else al[i:i + 1])
+                s.step_ps(u, dt, 1, ctx.variant, alphas=None if al is None else al[i:i + 1], forcing=ctx.forcing,
+                          step0=i)
                 states.append(u.clone())
             for i in reversed(range(start, end)):
-                s.vjp_ps(states[i - start], lam, dt, ctx.variant, alpha=None if al is None else al[i])
+                s.vjp_ps(states[i - start], lam, dt, ctx.variant, alpha=None if al is None else al[i],
+                         forcing=ctx.forcing, step=i)
         ctx.ckpts = None
-        return lam * w, None, None, None, None, None, None
+        return lam * w, None, None, None, None, None, None, None
 
 
 def final_energy(u):

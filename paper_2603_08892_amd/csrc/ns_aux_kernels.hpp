@@ -2,6 +2,7 @@
 #pragma once
 
 #include "ns_kernels.hpp"
+#include "ns_aux_types.hpp"
 
 namespace ns {
 
@@ -180,11 +181,11 @@ __device__ __forceinline__ int forcing_mode(int i, int* kx, int* ky, int* kz) {
 
 // One block of 64 threads: draw g for `step`, project it, scale it to inject
 // energy at rate `inj` over a step dt from state u, write the dense table
-// force[c][k_x+3][k_y+3][k_z] (k_z <= 3).
+// force[c][k_x+3][k_y+3][k_z] (k_z <= 3) and the FP64 record fs.
 template <typename R>
 __global__ void __launch_bounds__(64)
-k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int pitch, long long comp,
-          uint64_t seed, long long step, double dt, double inj) {
+k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, ForceState* __restrict__ fs, int n,
+          int pitch, long long comp, uint64_t seed, long long step, double dt, double inj) {
   __shared__ double gre[48][3], gim[48][3], pb[48], pg[48];
   __shared__ double amp;
   const int i = threadIdx.x;
@@ -233,18 +234,173 @@ k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, int n, int pit
   if (i == 0) {
     double B = 0, G = 0;
     for (int m = 0; m < 48; ++m) { B += pb[m]; G += pg[m]; }
-    amp = 2.0 * inj / (B + sqrt(B * B + 2.0 * dt * G * inj));
+    const double r = sqrt(B * B + 2.0 * dt * G * inj);
+    amp = 2.0 * inj / (B + r);
+    fs->amp = amp;
+    fs->B = B;
+    fs->G = G;
+    fs->r = r;
+    fs->injected = dt * (amp * B + 0.5 * amp * amp * dt * G);
   }
   __syncthreads();
   if (i < 48) {
     int kx, ky, kz;
     forcing_mode(i, &kx, &ky, &kz);
     for (int c = 0; c < 3; ++c) {
+      fs->g[i][c][0] = gre[i][c];
+      fs->g[i][c][1] = gim[i][c];
+    }
+    for (int c = 0; c < 3; ++c) {
       const double re = amp * gre[i][c], im = amp * gim[i][c];
       force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz] = cx(R(re), R(im));
       if (kz == 0) force[c * 196 + ((-kx + 3) * 7 + (-ky + 3)) * 4] = cx(R(re), R(-im));
     }
   }
+}
+
+// ------------------------------------------------------------------ forced step adjoint
+// The forcing O = a(u0) g depends on the state through B = <u0, g> (the
+// amplitude solves a B + a^2 dt/2 G = inj), with da/dB = -a/r.  With
+// mu_O = (dS_new/dO)^T lam = dt (E_h lam + E_dt mu1) for the Heun step (mu1 the
+// adjoint of the first stage), the step adjoint gains (da/dB) <mu_O, g> g.
+// k_forcing_adj_dot (one block, before lam is overwritten) forms the scalar
+// (da/dB) <mu_O, g> over the 96 forced full-grid modes (Parseval weights: 2 off
+// the k_z = 0 plane, 1 on it, where both k and -k are stored); k_forcing_adj_add
+// adds it times g to the result.
+template <typename R>
+__global__ void __launch_bounds__(64)
+k_forcing_adj_dot(const Cx<R>* __restrict__ lam, Lay ll, const Cx<R>* __restrict__ mu1, Lay lm,
+                  const R* __restrict__ eh, const R* __restrict__ edt, ForceState* __restrict__ fs, int n,
+                  double dt) {
+  __shared__ double part[64];
+  const int i = threadIdx.x;
+  double acc = 0.0;
+  if (i < 48) {
+    int kx, ky, kz;
+    forcing_mode(i, &kx, &ky, &kz);
+    const int k2 = kx * kx + ky * ky + kz * kz;
+    const double fh = (double)eh[k2], fd = (double)edt[k2];
+    for (int side = 0; side < (kz == 0 ? 2 : 1); ++side) {
+      const int sx = side ? -kx : kx, sy = side ? -ky : ky;
+      const int xi = (sx + n) % n, yi = (sy + n) % n;
+      const double w = (kz == 0) ? 1.0 : 2.0;
+      for (int c = 0; c < 3; ++c) {
+        const Cx<R> l = lam[c * ll.cs + lay_at(ll, xi, yi, kz, n)];
+        const Cx<R> m = mu1[c * lm.cs + lay_at(lm, xi, yi, kz, n)];
+        const double mre = dt * (fh * (double)l.re + fd * (double)m.re);
+        const double mim = dt * (fh * (double)l.im + fd * (double)m.im);
+        const double gre = fs->g[i][c][0], gim = side ? -fs->g[i][c][1] : fs->g[i][c][1];
+        acc += w * (mre * gre + mim * gim);
+      }
+    }
+  }
+  part[i] = acc;
+  __syncthreads();
+  if (i == 0) {
+    double t = 0.0;
+    for (int m = 0; m < 48; ++m) t += part[m];
+    fs->dot = -(fs->amp / fs->r) * t;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64)
+k_forcing_adj_add(Cx<R>* __restrict__ lam, Lay ll, const ForceState* __restrict__ fs, int n) {
+  const int i = threadIdx.x;
+  if (i >= 48) return;
+  int kx, ky, kz;
+  forcing_mode(i, &kx, &ky, &kz);
+  const double s = fs->dot;
+  for (int side = 0; side < (kz == 0 ? 2 : 1); ++side) {
+    const int sx = side ? -kx : kx, sy = side ? -ky : ky;
+    const int xi = (sx + n) % n, yi = (sy + n) % n;
+    for (int c = 0; c < 3; ++c) {
+      const long long o = c * ll.cs + lay_at(ll, xi, yi, kz, n);
+      const double gre = fs->g[i][c][0], gim = side ? -fs->g[i][c][1] : fs->g[i][c][1];
+      const Cx<R> v = lam[o];
+      lam[o] = cx(R((double)v.re + s * gre), R((double)v.im + s * gim));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ energy budget
+// Pass 1: E = 1/2 sum w |u|^2 and eps = nu sum w |k|^2 |u|^2 over the retained
+// modes of a state (any layout; entries outside the retained set are ignored),
+// per block in a fixed order: a grid-stride loop over (row, k_z < kzn), a
+// shuffle tree per wavefront, the wavefronts in order.
+constexpr int kBudgetBlocks = 256;
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_budget_partial(const Cx<R>* __restrict__ u, Lay lu, Geom g, double nu, double* __restrict__ partials) {
+  __shared__ double we[4], wd[4];
+  const uint32_t n = (uint32_t)g.n, kzn = (uint32_t)g.kzn;
+  const uint32_t total = n * n * kzn;
+  double e = 0.0, d = 0.0;
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < total; t += gridDim.x * 256u) {
+    const uint32_t row = t / kzn, kz = t - row * kzn;
+    const int xi = (int)(row / n), yi = (int)(row - (uint32_t)xi * n);
+    const int kx = kval(xi, g.n), ky = kval(yi, g.n);
+    if (!retained(g, kx, ky, (int)kz)) continue;
+    const long long idx = lay_at(lu, xi, yi, (int)kz, g.n);
+    const double w = (kz == 0 || 2 * (int)kz == g.n) ? 1.0 : 2.0;
+    double m2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const Cx<R> a = u[c * lu.cs + idx];
+      m2 += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+    }
+    const double em = 0.5 * w * m2;
+    e += em;
+    d += 2.0 * nu * (double)((long long)kx * kx + (long long)ky * ky + (long long)kz * kz) * em;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    e += __shfl_down(e, off);
+    d += __shfl_down(d, off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    we[wave] = e;
+    wd[wave] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = ((we[0] + we[1]) + we[2]) + we[3];
+    partials[2 * blockIdx.x + 1] = ((wd[0] + wd[1]) + wd[2]) + wd[3];
+  }
+}
+
+// Pass 2 (one wavefront): sum the partials in a fixed order and update the
+// record.  dt == 0 starts the budget at this state.  forced: add the injected
+// energy of the step from the forcing record.
+__global__ void __launch_bounds__(64)
+k_budget_step(const double* __restrict__ partials, int nblocks, Budget* __restrict__ b,
+              const ForceState* __restrict__ fs, double dt, int forced) {
+  const int lane = threadIdx.x;
+  double e = 0.0, d = 0.0;
+  for (int k = lane; k < nblocks; k += 64) {
+    e += partials[2 * k];
+    d += partials[2 * k + 1];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    e += __shfl_down(e, off);
+    d += __shfl_down(d, off);
+  }
+  if (lane != 0) return;
+  if (dt == 0.0) {
+    b->t = 0.0;
+    b->E0 = e;
+    b->int_eps = 0.0;
+    b->int_p = 0.0;
+    b->p_last = 0.0;
+  } else {
+    b->t += dt;
+    b->int_eps += 0.5 * dt * (b->eps + d);
+    const double inj = forced ? fs->injected : 0.0;
+    b->int_p += inj;
+    b->p_last = inj / dt;
+  }
+  b->E = e;
+  b->eps = d;
+  b->residual = e - b->E0 + b->int_eps - b->int_p;
 }
 
 }  // namespace ns

@@ -26,9 +26,10 @@ constexpr int kFastL = 16;
 constexpr int kFastLp = kFastL + 1;
 
 // Addressing: a block-uniform base pointer (a state component or scratch field)
-// plus a per-lane 32-bit element offset.  Every specialised size keeps a
-// component below 2^24 elements, so the byte offset fits 32 bits, the base stays
-// in scalar registers and the index arithmetic is 32-bit.
+// plus a per-lane 32-bit element offset.  Every offset stays inside one component
+// of at most N^2 (N/2 + 1) elements, and the specialised sizes keep 8 bytes times
+// that below 2^32 (FastCfg checks it), so the byte offset fits 32 bits, the base
+// stays in scalar registers and the index arithmetic is 32-bit.
 __device__ __forceinline__ Cx<float> ld_off(const Cx<float>* __restrict__ base, uint32_t off) {
   return *reinterpret_cast<const Cx<float>*>(reinterpret_cast<const char*>(base) + off * 8u);
 }
@@ -48,8 +49,9 @@ __device__ __forceinline__ Cx<float> ld_masked(const Cx<float>* __restrict__ bas
 }
 
 // Truncation test along one k_x line (fixed k_y, k_z) in 32-bit arithmetic
-// (|k_i| <= N/2 <= 128 here): every mask is k_x^2 <= hi2 and |k_x| <= xmax with
-// per-line thresholds (xmax from the pair conditions of double_alias_free).
+// (|k_i| <= N/2 <= 256 here, so |k|^2 < 2^18): every mask is k_x^2 <= hi2 and
+// |k_x| <= xmax with per-line thresholds (xmax from the pair conditions of
+// double_alias_free).
 struct LineTest {
   int hi2, xmax;
   __device__ __forceinline__ bool operator()(int kx) const {
@@ -89,6 +91,7 @@ struct LinePlan {
 template <typename XI, typename YP, typename ZP, int PZ_, typename XF>
 struct FastCfg {
   static constexpr int N = XI::N;
+  static_assert(8ull * N * N * (N / 2 + 1) < (1ull << 32), "32-bit byte offsets need 8 N^2 (N/2+1) < 2^32");
   static constexpr int PZ = PZ_;
   using XInv = XI;
   using Y = YP;
@@ -472,7 +475,11 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
     for (int c = 0; c < 3; ++c) {
       Cx<float>* out0 = a.out0 + c * a.lo0.cs;
       Cx<float>* out1 = use1 ? a.out1 + c * a.lo1.cs : nullptr;
-      const Cx<float> Nv = Fv[c];
+      Cx<float> Nv = Fv[c];
+      Cx<float> O = cx(0.f, 0.f);
+      if (op_forced(OP) && a.force != nullptr && k2 >= 4 && k2 <= 9)
+        O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
+      if (OP != OP_HEUN1) Nv = Nv + O;  // RK4 slopes N + O (zero for the other ops)
       Cx<float> s0 = cx(0.f, 0.f), s1 = cx(0.f, 0.f);
       if constexpr (need0) s0 = s0v[c][j];
       if constexpr (need1) s1 = s1v[c][j];
@@ -482,8 +489,6 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
       } else if (OP == OP_AVG) {
         v0 = scale(s1 + Nv, 0.5f);
       } else if (OP == OP_HEUN1) {
-        Cx<float> O = cx(0.f, 0.f);
-        if (a.force != nullptr && k2 >= 4 && k2 <= 9) O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
         v1 = scale(s0 + scale(Nv + O, dt), edt);
         v0 = scale(s0, edt) + scale(Nv + O + O, 0.5f * dt * eh);
       } else if (OP == OP_HEUN2) {

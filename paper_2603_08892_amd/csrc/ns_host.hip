@@ -5,39 +5,19 @@
 // and of the Runge-Kutta schemes (Eq. base-eq integrated with exact integrating
 // factors; RK4 in Lawson form, RK2 phase-shift exact / approx / random).
 #include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdio>
-#include <cstdlib>
-#include <algorithm>
-#include <cstring>
-#include <type_traits>
-#include <new>
-#include <string>
-#include <vector>
-
-#include "../../include/ns.h"
-#include "ns_adjoint.hpp"
-#include "ns_fast.hpp"
-#include "ns_fast_adjoint.hpp"
+#include "ns_host_impl.hpp"
 #include "ns_aux_kernels.hpp"
 #include "ns_model1d.hpp"
 
-using ns::Cx;
-using ns::EpiArgs;
-using ns::FftPlan;
-using ns::Geom;
-using ns::AdjArgs;
-using ns::LamArgs;
+namespace nsh {
+thread_local std::string g_last_error;
+}  // namespace nsh
+
+using namespace nsh;
 
 namespace {
 
-constexpr int kEpt = 8;     // points per thread in the strided passes
-constexpr int kEptZ = 16;   // points per thread in the contiguous (z) pass
-constexpr size_t kAlign = 256;
-constexpr int kSpecBlocks = 256;  // one block per CU; its wavefronts keep private LDS bins
-
-thread_local std::string g_last_error;
+using namespace nsh;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -64,23 +44,6 @@ bool factor_ok(int n, std::vector<int>* radices) {
   if (radices) *radices = r;
   return true;
 }
-
-struct Layout {
-  Geom g;
-  FftPlan plan;
-  int elem;          // bytes per complex element
-  int tx;            // threads of the strided passes
-  int ntz;           // k_z tiles over [0, kzn)
-  int ntzf;          // k_z tiles over [0, N/2]
-  int pz, tz;        // lines per block and threads of the z pass
-  int pa, ta;        // the same for the adjoint z pass (0: adjoint not available)
-  long long k2top;   // largest retained |k|^2
-  int nsh, nbins;
-  std::vector<int2> tiles;   // active (k_y index, k_z tile start)
-  int ntiles_active;
-  size_t off_tw, off_etab, off_force, off_tiles, off_w, off_s, off_a, off_spec, off_specout;
-  size_t total;
-};
 
 bool cube_family_host(int mask) { return mask == NS_MASK_CUBE || mask == NS_MASK_ROGALLO; }
 
@@ -230,211 +193,11 @@ bool make_layout(const ns_config* c, Layout* lay) {
   lay->off_a = take(3 * (size_t)g.wcomp * e);
   lay->off_spec = take((size_t)kSpecBlocks * lay->nbins * sizeof(double));
   lay->off_specout = take((size_t)lay->nbins * sizeof(double));
+  lay->off_fstate = take(sizeof(ns::ForceState));
+  lay->off_budget = take(sizeof(ns::Budget));
+  lay->off_bpart = take(2 * (size_t)ns::kBudgetBlocks * sizeof(double));
   lay->total = off;
   return true;
-}
-
-}  // namespace
-
-struct ns_ctx {
-  ns_config cfg;
-  hipStream_t stream;
-  Layout lay;
-  char* ws;
-  std::string err;
-  double* pin_spec = nullptr;    // pinned host copy of the last spectra reduction
-  hipEvent_t spec_ev = nullptr;  // recorded after that copy
-  bool spec_pending = false;     // a reduction was enqueued and not yet waited for
-  int fast = 0;       // N of the specialised FP32 passes in use (0: generic passes)
-  double etab_dt = -1.0;  // dt of the integrating-factor tables now in the workspace
-  // per-pass timing: events[2 i], events[2 i + 1] bracket launch i of pass tpass[i]
-  bool timing = false;
-  std::vector<hipEvent_t> events;
-  std::vector<int> tpass;
-  size_t tused = 0;
-  ~ns_ctx() {
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    if (spec_ev) (void)hipEventDestroy(spec_ev);
-    if (pin_spec) (void)hipHostFree(pin_spec);
-  }
-};
-
-namespace {
-
-ns_status fail(ns_ctx* c, ns_status s, const std::string& msg) {
-  if (c) c->err = msg;
-  else g_last_error = msg;
-  return s;
-}
-
-ns_status hip_check(ns_ctx* c, hipError_t e, const char* what) {
-  if (e == hipSuccess) return NS_OK;
-  return fail(c, NS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-bool aligned(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
-
-// Timing brackets around one pass launch (no-ops unless timing is enabled).
-hipError_t tstart(ns_ctx* c, int pass) {
-  if (!c->timing) return hipSuccess;
-  if (2 * c->tused + 2 > c->events.size()) {
-    for (int k = 0; k < 2; ++k) {
-      hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-      c->events.push_back(e);
-    }
-    c->tpass.push_back(pass);
-  }
-  c->tpass[c->tused] = pass;
-  return hipEventRecord(c->events[2 * c->tused], c->stream);
-}
-
-hipError_t tstop(ns_ctx* c) {
-  if (!c->timing) return hipSuccess;
-  hipError_t r = hipEventRecord(c->events[2 * c->tused + 1], c->stream);
-  ++c->tused;
-  return r;
-}
-
-template <typename R>
-struct Ptrs {
-  Cx<R>* tw;
-  R* eh;
-  R* edt;
-  Cx<R>* force;
-  int2* tiles;
-  Cx<R>* W;
-  Cx<R>* sb;
-  Cx<R>* ab;
-  double* spec;
-  double* specout;
-};
-
-template <typename R>
-Ptrs<R> ptrs(ns_ctx* c) {
-  const Layout& l = c->lay;
-  Ptrs<R> p;
-  p.tw = reinterpret_cast<Cx<R>*>(c->ws + l.off_tw);
-  p.eh = reinterpret_cast<R*>(c->ws + l.off_etab);
-  p.edt = p.eh + (l.k2top + 1);
-  p.force = reinterpret_cast<Cx<R>*>(c->ws + l.off_force);
-  p.tiles = reinterpret_cast<int2*>(c->ws + l.off_tiles);
-  p.W = reinterpret_cast<Cx<R>*>(c->ws + l.off_w);
-  p.sb = reinterpret_cast<Cx<R>*>(c->ws + l.off_s);
-  p.ab = reinterpret_cast<Cx<R>*>(c->ws + l.off_a);
-  p.spec = reinterpret_cast<double*>(c->ws + l.off_spec);
-  p.specout = reinterpret_cast<double*>(c->ws + l.off_specout);
-  return p;
-}
-
-size_t lds_strided(const Layout& l) { return (size_t)(2 * l.g.n + l.g.n * l.g.L) * l.elem; }
-
-// Layouts: the caller's arrays and the compact internal stage buffers.
-ns::Lay user_lay(const Layout& l) { return ns::Lay{l.g.h, l.g.comp}; }
-ns::Lay compact_lay(const Layout& l) { return ns::Lay{l.g.kzp, l.g.wcomp}; }
-ns::Shift make_shift(const double* s) {
-  ns::Shift sh;
-  sh.s[0] = s ? s[0] : 0.0;
-  sh.s[1] = s ? s[1] : 0.0;
-  sh.s[2] = s ? s[2] : 0.0;
-  sh.on = (s != nullptr && (s[0] != 0.0 || s[1] != 0.0 || s[2] != 0.0)) ? 1 : 0;
-  return sh;
-}
-size_t lds_z(const Layout& l) { return (size_t)(l.g.n + 3 * l.pz * l.g.n) * l.elem; }
-size_t lds_zadj(const Layout& l) { return (size_t)(l.g.n + (9 * l.pa * l.g.n) / 2) * l.elem; }
-
-template <typename K>
-hipError_t allow_lds(K kernel, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-template <typename R, int OP>
-hipError_t launch_xfwd(ns_ctx* c, const Ptrs<R>& p, const ns::Shift& sh, const EpiArgs<R>& a) {
-  const Layout& l = c->lay;
-  const size_t lds = lds_strided(l);
-  auto kern = ns::k_xfwd<R, kEpt, OP>;
-  hipError_t e = allow_lds(kern, lds);
-  if (e != hipSuccess) return e;
-  const int nblk = a.full ? l.g.n * l.ntzf : l.ntiles_active;
-  if (nblk == 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(nblk), dim3(l.tx), lds, c->stream, p.W, p.tw, sh, p.tiles, l.g, l.plan, a);
-  return hipGetLastError();
-}
-
-// Chaining of consecutive evaluations.  In: front_done = this evaluation's
-// x-inverse pass already ran (fused into the previous x-forward pass); feed = the
-// stage output that is the next evaluation's input (0 none, 1 out0, 2 out1) and
-// next_s its shift.  Out: fused = the next evaluation's x-inverse pass ran here
-// (only the specialised passes fuse, and only into a stage that is not in full
-// mode); an out1 that feeds is then not stored.
-struct Chain {
-  bool front_done = false;
-  int feed = 0;
-  const double* next_s = nullptr;
-  bool fused = false;
-};
-
-// Specialised FP32 passes for one compile-time size (same semantics and layout).
-template <typename C, int OP, int FEED>
-ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift& sh, const EpiArgs<float>& a,
-                    bool front, const ns::Shift& sh2) {
-  const Layout& l = c->lay;
-  const Geom& g = l.g;
-  Ptrs<float> p = ptrs<float>(c);
-  constexpr int N = C::N, P = C::PZ;
-  hipError_t e;
-  const int ntiles = l.ntiles_active;
-  if (ntiles > 0) {
-    if (front) {
-      if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
-      hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
-                         c->stream, in, lin, p.W, p.tw, sh, p.tiles, g);
-      if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
-    }
-    if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
-                       c->stream, p.W, p.tw, l.ntz, g);
-    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
-    if ((e = tstart(c, 2)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL((ns::f_zcross<typename C::Z, P>), dim3(N * N / P), dim3(P * C::Z::TPL), 0, c->stream,
-                       p.W, p.tw, g);
-    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
-    if ((e = tstart(c, 3)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, -1>), dim3(3 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
-                       c->stream, p.W, p.tw, l.ntz, g);
-    if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
-  }
-  const int nblk = a.full ? N * l.ntzf : ntiles;
-  if ((e = tstart(c, FEED ? 5 : 4)) != hipSuccess) return hip_check(c, e, "timing event");
-  if (nblk > 0)
-    hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP, FEED>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
-                       c->stream, p.W, p.tw, sh, sh2, p.tiles, g, a);
-  if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
-  return hip_check(c, hipGetLastError(), "nonlinear-term launch");
-}
-
-template <typename C, int OP>
-ns_status eval_fast_chain(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift& sh,
-                          const EpiArgs<float>& a, Chain* ch) {
-  const bool front = !(ch && ch->front_done);
-  const int feed = (ch && !a.full && c->lay.ntiles_active > 0) ? ch->feed : 0;
-  if (ch) ch->fused = false;
-  if constexpr (ns::op_can_feed(OP, 1)) {
-    if (feed == 1) {
-      ch->fused = true;
-      return eval_fast<C, OP, 1>(c, in, lin, sh, a, front, make_shift(ch->next_s));
-    }
-  }
-  if constexpr (ns::op_can_feed(OP, 2)) {
-    if (feed == 2) {
-      ch->fused = true;
-      return eval_fast<C, OP, 2>(c, in, lin, sh, a, front, make_shift(ch->next_s));
-    }
-  }
-  return eval_fast<C, OP, 0>(c, in, lin, sh, a, front, sh);
 }
 
 // One evaluation of the nonlinear term on `in` (layout lin) with the shift s (NULL
@@ -449,14 +212,14 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs
   hipError_t e;
   if constexpr (std::is_same<R, float>::value) {
     switch (c->fast) {
-      case 64: return eval_fast_chain<ns::Fast64, OP>(c, in, lin, sh, a, ch);
-      case 128: return eval_fast_chain<ns::Fast128, OP>(c, in, lin, sh, a, ch);
-      case 192: return eval_fast_chain<ns::Fast192, OP>(c, in, lin, sh, a, ch);
-      case 256: return eval_fast_chain<ns::Fast256, OP>(c, in, lin, sh, a, ch);
-      case 216: return eval_fast_chain<ns::Fast216, OP>(c, in, lin, sh, a, ch);
-      case 324: return eval_fast_chain<ns::Fast324, OP>(c, in, lin, sh, a, ch);
-      case 384: return eval_fast_chain<ns::Fast384, OP>(c, in, lin, sh, a, ch);
-      case 512: return eval_fast_chain<ns::Fast512, OP>(c, in, lin, sh, a, ch);
+      case 64: return fast_eval<64, OP>(c, in, lin, sh, a, ch);
+      case 128: return fast_eval<128, OP>(c, in, lin, sh, a, ch);
+      case 192: return fast_eval<192, OP>(c, in, lin, sh, a, ch);
+      case 256: return fast_eval<256, OP>(c, in, lin, sh, a, ch);
+      case 216: return fast_eval<216, OP>(c, in, lin, sh, a, ch);
+      case 324: return fast_eval<324, OP>(c, in, lin, sh, a, ch);
+      case 384: return fast_eval<384, OP>(c, in, lin, sh, a, ch);
+      case 512: return fast_eval<512, OP>(c, in, lin, sh, a, ch);
       default: break;
     }
   }
@@ -541,8 +304,31 @@ ns_status etab(ns_ctx* c, double dt) {
   return st;
 }
 
+// Draw the forcing of step `step` from the state x (layout lx) into the workspace
+// table and the FP64 forcing record.
 template <typename R>
-ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
+ns_status forcing_draw(ns_ctx* c, const Cx<R>* x, ns::Lay lx, const ns_forcing* fo, long long step, double dt) {
+  Ptrs<R> p = ptrs<R>(c);
+  hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(64), 0, c->stream, x, p.force, p.fstate, c->lay.g.n, lx.pitch,
+                     lx.cs, fo->seed, step, dt, fo->injection);
+  return hip_check(c, hipGetLastError(), "k_forcing launch");
+}
+
+// Energy-budget update from the state y (layout ly) after a step of length dt
+// (dt = 0: start the budget at y); no-op while the budget is off.
+template <typename R>
+ns_status budget_sample(ns_ctx* c, const Cx<R>* y, ns::Lay ly, double dt, bool forced) {
+  if (!c->budget) return NS_OK;
+  Ptrs<R> p = ptrs<R>(c);
+  hipLaunchKernelGGL(ns::k_budget_partial<R>, dim3(ns::kBudgetBlocks), dim3(256), 0, c->stream, y, ly, c->lay.g,
+                     c->cfg.nu, p.bpart);
+  hipLaunchKernelGGL(ns::k_budget_step, dim3(1), dim3(64), 0, c->stream, p.bpart, ns::kBudgetBlocks, p.budget,
+                     p.fstate, dt, forced ? 1 : 0);
+  return hip_check(c, hipGetLastError(), "budget launch");
+}
+
+template <typename R>
+ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps, const ns_forcing* fo, long long step0) {
   Cx<R>* s0 = static_cast<Cx<R>*>(u);
   Ptrs<R> p = ptrs<R>(c);
   const ns::Lay U = user_lay(c->lay), K = compact_lay(c->lay);
@@ -566,6 +352,11 @@ ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
     a.in1 = p.ab;
     a.out0 = p.ab;
     a.out1 = p.sb;
+    if (fo != nullptr) {
+      // the forcing of this step, drawn from its start state, enters all four slopes
+      if ((st = forcing_draw<R>(c, x, lx, fo, step0 + i, dt)) != NS_OK) return st;
+      a.force = p.force;
+    }
     Chain ch;
     ch.feed = 2;
     ch.front_done = fused;
@@ -579,10 +370,12 @@ ns_status rk4_t(ns_ctx* c, void* u, double dt, int nsteps) {
     f.in1 = p.ab;
     f.out0 = last ? s0 : xs;
     f.lo0 = last ? U : K;
+    f.force = a.force;
     ch.front_done = ch.fused;
     ch.feed = last ? 0 : 1;
     if ((st = eval<R, ns::OP_RK4_3>(c, p.sb, K, nullptr, f, &ch)) != NS_OK) return st;
     fused = ch.fused;
+    if ((st = budget_sample<R>(c, last ? s0 : xs, last ? U : K, dt, fo != nullptr)) != NS_OK) return st;
   }
   return NS_OK;
 }
@@ -613,7 +406,9 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
   // reads the caller's array (x), the last writes it back whole (y).
   Cx<R>* xs = p.W + 6 * c->lay.g.wcomp;
   bool fused = false;  // the next evaluation's x-inverse pass already ran
-  for (int i = 0; i < nsteps; ++i) {
+  // one step; the state after it is in y (layout ly)
+  auto step = [&](int i) -> ns_status {
+    ns_status st;
     const bool first = (i == 0), last = (i == nsteps - 1);
     Cx<R>* x = first ? s0 : xs;
     Cx<R>* y = last ? s0 : xs;
@@ -634,7 +429,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
       f.out0 = y;
       f.lo0 = ly;
       if ((st = eval<R, ns::OP_MID2>(c, p.sb, K, zero, f)) != NS_OK) return st;
-      continue;
+      return NS_OK;
     }
     if (variant == NS_EULER || variant == NS_EULER_PS) {
       // S = E_dt (S0 + dt N_a) with N_a = N(S0) or the two-shift average
@@ -646,14 +441,14 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
       f.lo0 = ly;
       if (variant == NS_EULER) {
         if ((st = eval<R, ns::OP_EUL>(c, x, lx, zero, f)) != NS_OK) return st;
-        continue;
+        return NS_OK;
       }
       EpiArgs<R> a = epi<R>(c, 0);
       a.out0 = p.ab;
       if ((st = eval<R, ns::OP_STORE>(c, x, lx, zero, a)) != NS_OK) return st;
       f.in1 = p.ab;
       if ((st = eval<R, ns::OP_EULAV>(c, x, lx, half, f)) != NS_OK) return st;
-      continue;
+      return NS_OK;
     }
     if (variant == NS_PS_EXACT || variant == NS_PS_EXACT8) {
       // midpoint RK2 with every evaluation the average over ns shifts: the first
@@ -696,7 +491,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
         }
         fused = ch.fused;
       }
-      continue;
+      return NS_OK;
     }
     // Heun: the first-stage shifts of this step and of the next (the x-forward pass
     // of the second stage runs the next step's first x-inverse pass)
@@ -716,10 +511,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     a.out0 = p.ab;
     a.out1 = p.sb;
     if (fo != nullptr) {
-      const Geom& g = c->lay.g;
-      hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(64), 0, c->stream, x, p.force, g.n, lx.pitch,
-                         lx.cs, fo->seed, step0 + i, dt, fo->injection);
-      if ((st = hip_check(c, hipGetLastError(), "k_forcing launch")) != NS_OK) return st;
+      if ((st = forcing_draw<R>(c, x, lx, fo, step0 + i, dt)) != NS_OK) return st;
       a.force = p.force;
     }
     Chain ch;
@@ -737,38 +529,16 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     ch.next_s = an;
     if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f, &ch)) != NS_OK) return st;
     fused = ch.fused;
+    return NS_OK;
+  };
+  for (int i = 0; i < nsteps; ++i) {
+    const bool last = (i == nsteps - 1);
+    if ((st = step(i)) != NS_OK) return st;
+    if ((st = budget_sample<R>(c, last ? s0 : xs, last ? U : K, dt, fo != nullptr)) != NS_OK) return st;
   }
   return NS_OK;
 }
 
-// Specialised FP32 passes of one transposed evaluation (same semantics and layout).
-template <typename C, int AOP>
-ns_status adj_eval_fast(ns_ctx* c, const Cx<float>* st, ns::Lay lst, const ns::Shift& sh,
-                        const LamArgs<float>& la, AdjArgs<float> aa) {
-  const Layout& l = c->lay;
-  const Geom& g = l.g;
-  Ptrs<float> p = ptrs<float>(c);
-  constexpr int N = C::N, P = C::PZ;
-  const int ntiles = l.ntiles_active;
-  if (ntiles > 0) {
-    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
-                       c->stream, st, lst, p.W, p.tw, sh, p.tiles, g);
-    hipLaunchKernelGGL(ns::f_xlam<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
-                       c->stream, la, p.W, p.tw, sh, p.tiles, g);
-    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(9 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
-                       c->stream, p.W, p.tw, l.ntz, g);
-    hipLaunchKernelGGL((ns::f_zadj<typename C::Z, P>), dim3(N * N / P), dim3(P * C::Z::TPL), 0, c->stream,
-                       p.W, p.tw, g);
-    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, -1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
-                       c->stream, p.W, p.tw, l.ntz, g);
-  }
-  aa.ntzf = l.ntzf;
-  const int nblk = aa.full ? N * l.ntzf : ntiles;
-  if (nblk > 0)
-    hipLaunchKernelGGL((ns::f_xadj<typename C::XFwd, AOP>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
-                       c->stream, p.W, p.tw, sh, p.tiles, g, aa);
-  return hip_check(c, hipGetLastError(), "adjoint launch");
-}
 
 // One transposed linearised evaluation at state `st` (layout lst) with shift s:
 // lam-pass input from `la`, adjoint stage combination AOP in the last pass.
@@ -782,14 +552,14 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
   hipError_t e;
   if constexpr (std::is_same<R, float>::value) {
     switch (c->fast) {
-      case 64: return adj_eval_fast<ns::Fast64, AOP>(c, st, lst, sh, la, aa);
-      case 128: return adj_eval_fast<ns::Fast128, AOP>(c, st, lst, sh, la, aa);
-      case 192: return adj_eval_fast<ns::Fast192, AOP>(c, st, lst, sh, la, aa);
-      case 256: return adj_eval_fast<ns::Fast256, AOP>(c, st, lst, sh, la, aa);
-      case 216: return adj_eval_fast<ns::Fast216, AOP>(c, st, lst, sh, la, aa);
-      case 324: return adj_eval_fast<ns::Fast324, AOP>(c, st, lst, sh, la, aa);
-      case 384: return adj_eval_fast<ns::Fast384, AOP>(c, st, lst, sh, la, aa);
-      case 512: return adj_eval_fast<ns::Fast512, AOP>(c, st, lst, sh, la, aa);
+      case 64: return fast_adj_eval<64, AOP>(c, st, lst, sh, la, aa);
+      case 128: return fast_adj_eval<128, AOP>(c, st, lst, sh, la, aa);
+      case 192: return fast_adj_eval<192, AOP>(c, st, lst, sh, la, aa);
+      case 256: return fast_adj_eval<256, AOP>(c, st, lst, sh, la, aa);
+      case 216: return fast_adj_eval<216, AOP>(c, st, lst, sh, la, aa);
+      case 324: return fast_adj_eval<324, AOP>(c, st, lst, sh, la, aa);
+      case 384: return fast_adj_eval<384, AOP>(c, st, lst, sh, la, aa);
+      case 512: return fast_adj_eval<512, AOP>(c, st, lst, sh, la, aa);
       default: break;
     }
   }
@@ -826,7 +596,8 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
 }
 
 template <typename R>
-ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, const double* alpha) {
+ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, const double* alpha,
+                const ns_forcing* fo, long long step) {
   const Cx<R>* u0 = static_cast<const Cx<R>*>(u0v);
   Cx<R>* lam = static_cast<Cx<R>*>(lamv);
   Ptrs<R> p = ptrs<R>(c);
@@ -892,11 +663,23 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
   f.li0 = U;
   f.out0 = p.ab;
   f.out1 = p.sb;
+  if (fo != nullptr) {
+    // the forward step's forcing, redrawn from u0 (the draw is counter-based)
+    if ((st = forcing_draw<R>(c, u0, U, fo, step, dt)) != NS_OK) return st;
+    f.force = p.force;
+  }
   if ((st = eval<R, ns::OP_HEUN1>(c, u0, U, al, f)) != NS_OK) return st;  // sb = S1
   LamArgs<R> l1 = lamargs(lam, U, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
   AdjArgs<R> a = adj(0);
   a.out0 = p.ab;
   if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, K, be, l1, a)) != NS_OK) return st;  // ab = mu1
+  const Geom& g = c->lay.g;
+  if (fo != nullptr) {
+    // the amplitude's dependence on u0: (da/dB) <mu_O, g>, formed while lam is still the input
+    hipLaunchKernelGGL(ns::k_forcing_adj_dot<R>, dim3(1), dim3(64), 0, c->stream, lam, U, p.ab, K, p.eh, p.edt,
+                       p.fstate, g.n, dt);
+    if ((st = hip_check(c, hipGetLastError(), "k_forcing_adj_dot launch")) != NS_OK) return st;
+  }
   LamArgs<R> l2 = lamargs(lam, U, R(0.5) * rdt, p.eh, p.ab, rdt, p.edt);
   AdjArgs<R> b = adj(1);
   b.in0 = lam;
@@ -904,7 +687,12 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
   b.in1 = p.ab;
   b.out0 = lam;
   b.lo0 = U;
-  return adj_eval<R, ns::AOP_HEUN>(c, u0, U, al, l2, b);
+  if ((st = adj_eval<R, ns::AOP_HEUN>(c, u0, U, al, l2, b)) != NS_OK) return st;
+  if (fo != nullptr) {
+    hipLaunchKernelGGL(ns::k_forcing_adj_add<R>, dim3(1), dim3(64), 0, c->stream, lam, U, p.fstate, g.n);
+    if ((st = hip_check(c, hipGetLastError(), "k_forcing_adj_add launch")) != NS_OK) return st;
+  }
+  return NS_OK;
 }
 
 // Enqueue the reduction and its copy into pinned host memory, then record an
@@ -958,6 +746,27 @@ ns_status spectra_wait(ns_ctx* c, ns_spectra_out* out) {
   if (out->e_1d) std::memcpy(out->e_1d, b + 3 * nsh, 3 * h * sizeof(double));
   if (out->totals) std::memcpy(out->totals, b + 3 * nsh + 3 * h, 5 * sizeof(double));
   if (b[3 * nsh + 3 * h + 4] != 0.0) return fail(c, NS_ERR_NONFINITE, "non-finite entries in input");
+  return NS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Host checks of a forcing argument (NULL is valid: no forcing).
+ns_status check_forcing(ns_ctx* ctx, const ns_forcing* forcing) {
+  if (forcing == nullptr) return NS_OK;
+  if (forcing->k2_lo != 4 || forcing->k2_hi != 9) return fail(ctx, NS_ERR_ARG, "forcing shell must be 4 <= |k|^2 <= 9");
+  if (!(forcing->injection > 0.0) || !std::isfinite(forcing->injection))
+    return fail(ctx, NS_ERR_ARG, "injection must be finite and > 0");
+  const Geom& g = ctx->lay.g;
+  for (int kx = -3; kx <= 3; ++kx)
+    for (int ky = -3; ky <= 3; ++ky)
+      for (int kz = 0; kz <= 3; ++kz) {
+        const int k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 >= 4 && k2 <= 9 && !retained_host(g, kx, ky, kz))
+          return fail(ctx, NS_ERR_ARG, "forcing shell lies outside the retained set");
+      }
   return NS_OK;
 }
 
@@ -1021,6 +830,15 @@ ns_status ns_init(const ns_config* cfg, void* workspace, size_t ws_bytes, ns_ctx
   if (e == hipSuccess && !c->lay.tiles.empty())
     e = hipMemcpyAsync(c->ws + c->lay.off_tiles, c->lay.tiles.data(), c->lay.tiles.size() * sizeof(int2),
                        hipMemcpyHostToDevice, c->stream);
+  // the FP64 records start at zero (an empty budget, no forcing drawn yet)
+  const std::vector<char> zero(sizeof(ns::ForceState) + sizeof(ns::Budget), 0);
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(c->ws + c->lay.off_fstate, zero.data(), sizeof(ns::ForceState), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ws + c->lay.off_budget, zero.data(), sizeof(ns::Budget), hipMemcpyHostToDevice,
+                         c->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     std::string msg = std::string("upload of tables failed: ") + hipGetErrorString(e);
@@ -1056,14 +874,17 @@ ns_status ns_nonlinear(ns_ctx* ctx, const void* u_hat, void* n_hat, const double
                                        : nonlinear_t<double>(ctx, u_hat, n_hat, shift, flags);
 }
 
-ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps) {
+ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps, const ns_forcing* forcing,
+                            int64_t step0) {
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
   if (!aligned(u_hat)) return fail(ctx, NS_ERR_ARG, "u_hat must be a non-NULL 256-byte aligned device pointer");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(ctx, NS_ERR_ARG, "nsteps must be >= 0");
+  ns_status st = check_forcing(ctx, forcing);
+  if (st != NS_OK) return st;
   if (nsteps == 0) return NS_OK;
-  return ctx->cfg.precision == NS_FP32 ? rk4_t<float>(ctx, u_hat, dt, nsteps)
-                                       : rk4_t<double>(ctx, u_hat, dt, nsteps);
+  return ctx->cfg.precision == NS_FP32 ? rk4_t<float>(ctx, u_hat, dt, nsteps, forcing, step0)
+                                       : rk4_t<double>(ctx, u_hat, dt, nsteps, forcing, step0);
 }
 
 ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps, int32_t variant,
@@ -1073,20 +894,10 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(ctx, NS_ERR_ARG, "nsteps must be >= 0");
   if (variant < NS_PS_EXACT || variant > NS_PS_EXACT8) return fail(ctx, NS_ERR_ARG, "unknown scheme variant");
-  if (forcing) {
-    if (variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
-      return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
-    if (forcing->k2_lo != 4 || forcing->k2_hi != 9) return fail(ctx, NS_ERR_ARG, "forcing shell must be 4 <= |k|^2 <= 9");
-    if (!(forcing->injection > 0.0) || !std::isfinite(forcing->injection)) return fail(ctx, NS_ERR_ARG, "injection must be finite and > 0");
-    const Geom& g = ctx->lay.g;
-    for (int kx = -3; kx <= 3; ++kx)
-      for (int ky = -3; ky <= 3; ++ky)
-        for (int kz = 0; kz <= 3; ++kz) {
-          const int k2 = kx * kx + ky * ky + kz * kz;
-          if (k2 >= 4 && k2 <= 9 && !retained_host(g, kx, ky, kz))
-            return fail(ctx, NS_ERR_ARG, "forcing shell lies outside the retained set");
-        }
-  }
+  if (forcing && variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
+    return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
+  ns_status fst = check_forcing(ctx, forcing);
+  if (fst != NS_OK) return fst;
   if (alphas && variant == NS_PS_RANDOM)
     for (int i = 0; i < 3 * nsteps; ++i)
       if (!std::isfinite(alphas[i])) return fail(ctx, NS_ERR_ARG, "alphas must be finite");
@@ -1186,6 +997,7 @@ ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches) {
   ns_status st = hip_check(ctx, hipStreamSynchronize(ctx->stream), "timing synchronize");
   if (st != NS_OK) return st;
   for (size_t i = 0; i < ctx->tused; ++i) {
+    if (ctx->tpass[i] < 0 || ctx->tpass[i] >= NS_NUM_PASSES) return fail(ctx, NS_ERR_ARG, "pass id out of range");
     float t = 0.f;
     st = hip_check(ctx, hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]), "timing elapsed");
     if (st != NS_OK) return st;
@@ -1201,7 +1013,7 @@ ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches) {
 }
 
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt, int32_t variant,
-                                const double alpha[3]) {
+                                const double alpha[3], const ns_forcing* forcing, int64_t step) {
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
   if (!aligned(u_hat0) || !aligned(lam)) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must be non-NULL 256-byte aligned device pointers");
   if (u_hat0 == lam) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must not overlap");
@@ -1212,8 +1024,40 @@ ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, doub
                                   !std::isfinite(alpha[2])))
     return fail(ctx, NS_ERR_ARG, "NS_PS_RANDOM needs the finite first-stage shift alpha");
   if (ctx->lay.pa == 0) return fail(ctx, NS_ERR_ARG, "the adjoint supports n <= 910");
-  return ctx->cfg.precision == NS_FP32 ? vjp_t<float>(ctx, u_hat0, lam, dt, variant, alpha)
-                                       : vjp_t<double>(ctx, u_hat0, lam, dt, variant, alpha);
+  if (forcing && variant == NS_PS_EXACT) return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
+  ns_status st = check_forcing(ctx, forcing);
+  if (st != NS_OK) return st;
+  return ctx->cfg.precision == NS_FP32 ? vjp_t<float>(ctx, u_hat0, lam, dt, variant, alpha, forcing, step)
+                                       : vjp_t<double>(ctx, u_hat0, lam, dt, variant, alpha, forcing, step);
+}
+
+ns_status ns_budget_start(ns_ctx* ctx, const void* u_hat) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!aligned(u_hat)) return fail(ctx, NS_ERR_ARG, "u_hat must be a non-NULL 256-byte aligned device pointer");
+  ctx->budget = true;
+  const ns::Lay U = user_lay(ctx->lay);
+  return ctx->cfg.precision == NS_FP32
+             ? budget_sample<float>(ctx, static_cast<const Cx<float>*>(u_hat), U, 0.0, false)
+             : budget_sample<double>(ctx, static_cast<const Cx<double>*>(u_hat), U, 0.0, false);
+}
+
+ns_status ns_budget_stop(ns_ctx* ctx) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  ctx->budget = false;
+  return NS_OK;
+}
+
+ns_status ns_budget_read(ns_ctx* ctx, double* out) {
+  if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
+  if (!out) return fail(ctx, NS_ERR_ARG, "out is NULL");
+  ns::Budget b;
+  ns_status st = hip_check(ctx, hipMemcpyAsync(&b, ctx->ws + ctx->lay.off_budget, sizeof(b), hipMemcpyDeviceToHost,
+                                               ctx->stream), "budget copy");
+  if (st == NS_OK) st = hip_check(ctx, hipStreamSynchronize(ctx->stream), "budget wait");
+  if (st != NS_OK) return st;
+  const double v[NS_BUDGET_LEN] = {b.t, b.E, b.eps, b.E0, b.int_eps, b.int_p, b.p_last, b.residual};
+  std::memcpy(out, v, sizeof(v));
+  return NS_OK;
 }
 
 }  // extern "C"

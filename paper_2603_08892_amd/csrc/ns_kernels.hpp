@@ -326,7 +326,7 @@ enum EpiOp {
   OP_HEUN2 = 3,  // out0 = in1 + dt/2 E_h N
   OP_EX1B = 4,   // out0 = E_h (S0 + dt/2 w (in1 + N))
   OP_EX2B = 5,   // out0 = E_dt S0 + dt E_h w (in1 + N)
-  OP_RK4_0 = 6,  // out1 = E_h (S0 + dt/2 N); out0 = E_dt S0 + dt/6 E_dt N
+  OP_RK4_0 = 6,  // out1 = E_h (S0 + dt/2 N); out0 = E_dt S0 + dt/6 E_dt N   (N: slope N + O)
   OP_RK4_1 = 7,  // out1 = E_h S0 + dt/2 N;   out0 = in1 + dt/3 E_h N
   OP_RK4_2 = 8,  // out1 = E_dt S0 + dt E_h N; out0 = in1 + dt/3 E_h N
   OP_RK4_3 = 9,  // out0 = in1 + dt/6 N
@@ -338,6 +338,13 @@ enum EpiOp {
 };
 // w (EpiArgs::w) weighs each of the shifted evaluations summed in in1 + N: 1/2 for
 // the two-shift average, 1/8 for the average over the eight shifts in {0, 1/2}^3.
+
+// Ops that take the forcing O (EpiArgs::force, when non-null): the first Heun stage
+// (which also carries the second stage's O into out0) and every RK4 stage, whose
+// slope is N + O.
+__host__ __device__ constexpr bool op_forced(int op) {
+  return op == OP_HEUN1 || op == OP_RK4_0 || op == OP_RK4_1 || op == OP_RK4_2 || op == OP_RK4_3;
+}
 
 // Ops whose stage formula uses the integrating factors E_h and E_dt.
 __host__ __device__ constexpr bool op_uses_etab(int op) {
@@ -463,15 +470,16 @@ k_xfwd(const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ twg, Shift sh,
     for (int c = 0; c < 3; ++c) {
       const long long o0 = c * a.lo0.cs + io0, o1 = c * a.lo1.cs + io1;
       const long long i0 = c * a.li0.cs + ii0, i1 = c * a.li1.cs + ii1;
-      const Cx<R> N = F[c];
+      Cx<R> N = F[c];
+      Cx<R> O = cx(R(0), R(0));
+      if (op_forced(OP) && a.force != nullptr && k2 >= 4 && k2 <= 9)
+        O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
+      if (OP != OP_HEUN1) N = N + O;  // RK4 slopes N + O (zero for the other ops)
       if (OP == OP_STORE) {
         a.out0[o0] = N;
       } else if (OP == OP_AVG) {
         a.out0[o0] = scale(a.in1[i1] + N, R(0.5));
       } else if (OP == OP_HEUN1) {
-        Cx<R> O = cx(R(0), R(0));
-        if (a.force != nullptr && k2 >= 4 && k2 <= 9)
-          O = a.force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz];
         const Cx<R> s0 = a.in0[i0];
         a.out1[o1] = scale(s0 + scale(N + O, dt), edt);
         a.out0[o0] = scale(s0, edt) + scale(N + O + O, R(0.5) * dt * eh);

@@ -95,6 +95,25 @@ def hit_initial(n, seed, k2max, energy=1.5, kpeak=4.0):
                              energy=energy)
 
 
+def embed(a, n):
+    """A spectral field of an m^3 grid, zero at and beyond |k_i| = m/2, placed at the same
+    wavevectors of an n^3 grid (n >= m): the same physical field on the finer grid."""
+    m = a.shape[-2]
+    out = np.zeros(a.shape[:-3] + (n, n, n // 2 + 1), dtype=a.dtype)
+    k = _axis_k(m)
+    idx = k % n
+    out[..., idx[:, None], idx[None, :], : m // 2] = a[..., :, :, : m // 2]
+    return out
+
+
+def hit_field(n, seed, k2max, energy=1.5, kpeak=4.0, base=64):
+    """The field of hit_initial drawn on a base^3 grid (|k| < base/2; the spectrum
+    k^4 exp(-2 (k/4)^2) is below 1e-10 of its peak there) and embedded in the n^3 grid,
+    so that every grid n >= base starts from the same physical field."""
+    k2 = min(k2max, (base // 2 - 1) ** 2)
+    return embed(hit_initial(base, seed, k2, energy=energy, kpeak=kpeak), n)
+
+
 def tg_perturbed(n, seed, k2max, rel=1e-2):
     """Taylor-Green plus a random divergence-free perturbation whose L2 norm is `rel`
     times that of the Taylor-Green field."""

@@ -31,7 +31,10 @@ VARIANTS = {"exact": NS_PS_EXACT, "approx": NS_PS_APPROX, "random": NS_PS_RANDOM
 ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns_init", "ns_destroy",
                  "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
                  "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift", "ns_timing_enable",
-                 "ns_timing_read", "ns1d_nonlinear", "ns1d_step", "ns_spectra_async", "ns_spectra_wait")
+                 "ns_timing_read", "ns1d_nonlinear", "ns1d_step", "ns_spectra_async", "ns_spectra_wait",
+                 "ns_budget_start", "ns_budget_stop", "ns_budget_read")
+NS_BUDGET_LEN = 8
+BUDGET_NAMES = ("t", "E", "eps", "E0", "int_eps", "int_p", "p_last", "residual")
 PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue", "x_forward_inverse")
 
 
@@ -79,10 +82,13 @@ def lib():
         "ns_last_error": (ctypes.c_char_p, [P]),
         "ns_set_stream": (I32, [P, P]),
         "ns_nonlinear": (I32, [P, P, P, P, I32]),
-        "ns_step_rk4_trunc": (I32, [P, P, D, I32]),
+        "ns_step_rk4_trunc": (I32, [P, P, D, I32, ctypes.POINTER(NSForcing), I64]),
         "ns_step_rk2_phaseshift": (I32, [P, P, D, I32, I32, P, ctypes.POINTER(NSForcing), I64]),
         "ns_spectra": (I32, [P, P, P, ctypes.POINTER(NSSpectraOut)]),
-        "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P]),
+        "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P, ctypes.POINTER(NSForcing), I64]),
+        "ns_budget_start": (I32, [P, P]),
+        "ns_budget_stop": (I32, [P]),
+        "ns_budget_read": (I32, [P, P]),
         "ns_timing_enable": (I32, [P, I32]),
         "ns_timing_read": (I32, [P, P, P]),
         "ns_spectra_async": (I32, [P, P, P]),
@@ -116,6 +122,13 @@ def retained_bound(n, ct, mask="sphere"):
 
 def num_shells(n):
     return int(lib().ns_num_shells(int(n)))
+
+
+def _forcing(f):
+    """ns_forcing from dict(seed=..., injection=1.0) (the shell 4 <= |k|^2 <= 9), or NULL."""
+    if f is None:
+        return None
+    return ctypes.byref(NSForcing(4, 9, float(f.get("injection", 1.0)), int(f["seed"])))
 
 
 def _dbl3(v):
@@ -167,8 +180,11 @@ class Solver:
         return ctypes.c_void_p(t.data_ptr())
 
     def _sync_stream(self):
+        """Follow torch's current stream.  The workspace is shared by every call, so the
+        new stream first waits for the work already enqueued on the old one."""
         cur = self.torch.cuda.current_stream(self.device)
         if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
             self.stream = cur
             self._check(lib().ns_set_stream(self.ctx, ctypes.c_void_p(cur.cuda_stream)))
 
@@ -188,9 +204,11 @@ class Solver:
                                        _dbl3(shift), NS_NL_PS_AVG if ps_avg else 0))
         return out
 
-    def step_rk4(self, u, dt, nsteps=1):
+    def step_rk4(self, u, dt, nsteps=1, forcing=None, step0=0):
+        """Lawson RK4 steps in place; forcing: dict(seed=..., injection=1.0) or None."""
         self._sync_stream()
-        self._check(lib().ns_step_rk4_trunc(self.ctx, self._field(u, "u"), float(dt), int(nsteps)))
+        self._check(lib().ns_step_rk4_trunc(self.ctx, self._field(u, "u"), float(dt), int(nsteps),
+                                            _forcing(forcing), int(step0)))
         return u
 
     def step_ps(self, u, dt, nsteps=1, variant="random", alphas=None, forcing=None, step0=0):
@@ -206,11 +224,8 @@ class Solver:
             if a.size != 3 * int(nsteps):
                 raise ValueError("alphas must have shape [nsteps, 3]")
             ap = a.ctypes.data_as(ctypes.c_void_p)
-        fo = None
-        if forcing is not None:
-            fo = ctypes.byref(NSForcing(4, 9, float(forcing.get("injection", 1.0)), int(forcing["seed"])))
         self._check(lib().ns_step_rk2_phaseshift(self.ctx, self._field(u, "u"), float(dt), int(nsteps),
-                                                 VARIANTS[variant], ap, fo, int(step0)))
+                                                 VARIANTS[variant], ap, _forcing(forcing), int(step0)))
         return u
 
     def _spectra_out(self):
@@ -244,12 +259,29 @@ class Solver:
         out, so = self._spectra_out()
         return self._spectra_status(lib().ns_spectra_wait(self.ctx, ctypes.byref(so)), out, check_finite)
 
-    def vjp_ps(self, u0, lam, dt, variant="random", alpha=None):
-        """In place: lam <- (dS_new/dS_0)^T lam for one unforced phase-shift RK2 step at u0."""
+    def vjp_ps(self, u0, lam, dt, variant="random", alpha=None, forcing=None, step=0):
+        """In place: lam <- (dS_new/dS_0)^T lam for one phase-shift RK2 step at u0 (forced with
+        the draw of `step` when forcing is a dict(seed=..., injection=...))."""
         self._sync_stream()
         self._check(lib().ns_vjp_rk2_phaseshift(self.ctx, self._field(u0, "u0"), self._field(lam, "lam"),
-                                                float(dt), VARIANTS[variant], _dbl3(alpha)))
+                                                float(dt), VARIANTS[variant], _dbl3(alpha), _forcing(forcing),
+                                                int(step)))
         return lam
+
+    def budget_start(self, u):
+        """Start the FP64 energy budget at state u; every later step updates it on the device."""
+        self._sync_stream()
+        self._check(lib().ns_budget_start(self.ctx, self._field(u, "u")))
+
+    def budget_stop(self):
+        self._check(lib().ns_budget_stop(self.ctx))
+
+    def budget_read(self):
+        """{t, E, eps, E0, int_eps, int_p, p_last, residual} (waits for the stream)."""
+        self._sync_stream()
+        out = np.zeros(NS_BUDGET_LEN)
+        self._check(lib().ns_budget_read(self.ctx, out.ctypes.data_as(ctypes.c_void_p)))
+        return {k: float(out[i]) for i, k in enumerate(BUDGET_NAMES)}
 
     def timing(self, enable):
         """Enable or disable per-pass event timing on this context."""

@@ -756,3 +756,31 @@ def test_budget_taylor_green_and_forced_orders():
         assert abs(sum(inj) - T) < 1e-12
         res.append(spectra.budget(e, eps, inj, dt)[-1])
     assert abs(res[0]) < 0.05 * T and abs(res[0] / res[1] - 2) < 0.4, res
+
+
+def test_forced_step_vjp_against_finite_differences():
+    """The adjoint of the forced Heun step, with the forcing redrawn from the perturbed
+    state (its amplitude depends on u0 through the unit-injection rule), against
+    Richardson-extrapolated central differences of the forced step (FP64)."""
+    n, nu, dt, seed, step = 12, 0.02, 0.05, 9, 4
+    m = grid.mask(n, 1.0)
+    k2max = grid.sphere_k2max(n, 1.0)
+    model = onl.NSModel(n, nu, m)
+    s0 = inputs.hit_initial(n, 21, k2max)
+    lam = inputs.random_solenoidal(n, 22, k2max)
+    al = (0.3, 0.9, 0.05)
+
+    def f(s):
+        return schemes.ps_heun(model, s, dt, al, forcing=forcing.forcing(s, dt, seed, step))
+
+    g = schemes.ps_heun_vjp(model, s0, lam, dt, al, forcing=forcing.forcing(s0, dt, seed, step),
+                            forcing_vjp=forcing.forcing_vjp(s0, dt, seed, step))
+    g0 = schemes.ps_heun_vjp(model, s0, lam, dt, al, forcing=forcing.forcing(s0, dt, seed, step))
+    for vs in range(3):
+        v = inputs.random_solenoidal(n, 40 + vs, k2max)
+        d = [(f(s0 + e * v) - f(s0 - e * v)) / (2 * e) for e in (1e-3, 5e-4)]
+        jv = (4 * d[1] - d[0]) / 3
+        lhs, rhs = _dot(lam, jv), _dot(g, v)
+        assert abs(lhs - rhs) <= 1e-8 * max(abs(lhs), 1e-12), (lhs, rhs)
+        # without the amplitude term the adjoint is measurably wrong
+        assert abs(lhs - _dot(g0, v)) > 1e-6 * abs(lhs)
