@@ -118,6 +118,24 @@ def forcing(uh0, dt, seed, step):
     return amplitude(uh0, g, dt) * g
 
 
+def forcing_vjp(uh0, dt, seed, step):
+    """Transpose of the derivative of the forcing O(u0) = a(u0) g with respect to u0,
+    as a map mu -> (dO/du0)^T mu (Parseval inner product).  Only the amplitude
+    depends on u0, through B = <u0, g>: from a B + a^2 dt/2 G = 1,
+    da/dB = -a / sqrt(B^2 + 2 dt G), so (dO/du0)^T mu = (da/dB) <mu, g> g."""
+    n = uh0.shape[-2]
+    w = grid.hermitian_weight(n)
+    g = forcing_shape(n, seed, step)
+    b = float(np.sum(w * np.real(np.conj(uh0) * g)))
+    gg = float(np.sum(w * np.abs(g) ** 2))
+    r = math.sqrt(b * b + 2.0 * dt * gg)
+    dadb = -(2.0 / (b + r)) / r
+
+    def apply(mu):
+        return dadb * float(np.sum(w * np.real(np.conj(mu) * g))) * g
+    return apply
+
+
 def injected(uh0, o, dt):
     """Energy the forcing O puts into the state over one step of length dt from
     u_hat0: E(u0 + dt O) - E(u0) = dt sum w Re(conj(u0).O) + dt^2/2 sum w |O|^2.

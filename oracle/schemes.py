@@ -113,20 +113,27 @@ def ps_heun(model, s0, dt, alpha, beta=None, forcing=None):
 
 
 # --------------------------------------------------------------------------- adjoints
-def ps_heun_vjp(model, s0, lam, dt, alpha, beta=None):
-    """Transpose of the linearised (unforced) Heun step at S0 applied to lam = dJ/dS_new.
+def ps_heun_vjp(model, s0, lam, dt, alpha, beta=None, forcing=None, forcing_vjp=None):
+    """Transpose of the linearised Heun step at S0 applied to lam = dJ/dS_new.
 
-    S1 = E_dt(S0 + dt N_a(S0)), S_new = E_dt S0 + dt/2 E_h (N_a(S0) + N_b(S1)), so
-    mu1 = dJ/dS1 = dt/2 dN_b[S1]^T (E_h lam) and
+    S1 = E_dt(S0 + dt (N_a(S0) + O)), S_new = E_dt S0 + dt/2 E_h (N_a(S0) + N_b(S1) + 2 O),
+    so mu1 = dJ/dS1 = dt/2 dN_b[S1]^T (E_h lam) and
     dJ/dS0 = E_dt (lam + mu1) + dN_a[S0]^T (dt/2 E_h lam + dt E_dt mu1).
+    forcing: the O of the forward step (None: unforced).  When O depends on S0,
+    forcing_vjp maps mu_O = dJ/dO = dt (E_h lam + E_dt mu1) to its contribution
+    (dO/dS0)^T mu_O, which is added.
     """
     if beta is None:
         beta = beta_of(alpha)
+    o = 0.0 if forcing is None else forcing
     edt = model.E(dt)
     eh = model.E(0.5 * dt)
-    s1 = edt * (s0 + dt * model.nl(s0, alpha))
+    s1 = edt * (s0 + dt * (model.nl(s0, alpha) + o))
     mu1 = 0.5 * dt * model.nl_vjp(s1, eh * lam, beta)
-    return edt * (lam + mu1) + model.nl_vjp(s0, 0.5 * dt * eh * lam + dt * edt * mu1, alpha)
+    out = edt * (lam + mu1) + model.nl_vjp(s0, 0.5 * dt * eh * lam + dt * edt * mu1, alpha)
+    if forcing_vjp is not None:
+        out = out + forcing_vjp(dt * (eh * lam + edt * mu1))
+    return out
 
 
 def ps_exact_vjp(model, s0, lam, dt):
