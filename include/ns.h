@@ -220,6 +220,22 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
  * n_hat is NaN or Inf. */
 ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the spectra of ns_spectra without a
+ * context and without any allocation, device or host.  The FP64 partials and bins
+ * live in a file-scope device array of the library, about 4.3 MB on each GPU it
+ * runs on (held until the process ends; its address is looked up once per device,
+ * at the first call on that device).  n: 2^a 3^b 5^c, 8 <= n <= NS_SPECTRA_STATIC_MAX_N
+ * (NS_ERR_SIZE above it); precision: ns_precision of u_hat and n_hat (state
+ * layout, 256-byte aligned device pointers; n_hat may be NULL); nu >= 0 for the
+ * dissipation.  Enqueued on `stream` and waited for; outputs and errors as
+ * ns_spectra, with the same bit-for-bit results.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other host threads, other streams)
+ * race. */
+#define NS_SPECTRA_STATIC_MAX_N 512
+ns_status ns_spectra_static(int32_t n, int32_t precision, double nu, const void* u_hat, const void* n_hat,
+                            void* stream, ns_spectra_out* out);
+
 /* The same in two halves, so that a time loop keeps the GPU busy while the host
  * waits: ns_spectra_async enqueues the reduction of u_hat (and n_hat) as they are
  * at that point of the stream, with its copy into pinned host memory the library

@@ -5,6 +5,9 @@
 // and of the Runge-Kutta schemes (Eq. base-eq integrated with exact integrating
 // factors; RK4 in Lawson form, RK2 phase-shift exact / approx / random).
 #include <hip/hip_runtime.h>
+
+#include <mutex>
+
 #include "ns_host_impl.hpp"
 #include "ns_aux_kernels.hpp"
 #include "ns_model1d.hpp"
@@ -975,6 +978,101 @@ ns_status ns_spectra_wait(ns_ctx* ctx, ns_spectra_out* out) {
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
   if (!out) return fail(ctx, NS_ERR_ARG, "out is NULL");
   return spectra_wait(ctx, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- spectra without allocation
+// ns_spectra_static keeps the FP64 partials and the summed bins in this array: one
+// copy per GPU, held until the process ends, shared by every call on that GPU.
+// Every entry a call reads is written by the same call first (each block writes all
+// of its bins, the second pass every output bin), so nothing needs clearing.
+namespace {
+
+constexpr int kStaticMaxN = NS_SPECTRA_STATIC_MAX_N;
+constexpr int static_nbins(int n) {
+  // 3 shell spectra, 3 one-dimensional spectra of n/2 + 1 bins, 5 totals; shells as num_shells
+  return 3 * (int)(1.7320508075688772 * (n / 2) + 2) + 3 * (n / 2 + 1) + 5;
+}
+constexpr size_t kStaticDoubles = (size_t)(kSpecBlocks + 1) * static_nbins(kStaticMaxN);
+__device__ __align__(256) double scratch[kStaticDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up once per device, with the
+// device current).
+ns_status scratch_for_current_device(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, NS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, NS_ERR_STATE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(nullptr, NS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return NS_OK;
+}
+
+template <typename R>
+ns_status spectra_static_t(int n, double nu, const void* u, const void* nh, hipStream_t stream,
+                           ns_spectra_out* out) {
+  const int h = n / 2 + 1, nsh = num_shells(n), nbins = 3 * nsh + 3 * h + 5;
+  double* base = nullptr;
+  ns_status st = scratch_for_current_device(&base);
+  if (st != NS_OK) return st;
+  double* partials = base;
+  double* bins = base + (size_t)kSpecBlocks * nbins;
+  const size_t set = (size_t)nbins * sizeof(double);
+  const int nwb = (int)std::max<size_t>(1, std::min<size_t>(16, (size_t)(128 * 1024) / set));
+  const size_t lds = nwb * set;
+  hipError_t e = allow_lds(ns::k_spectra<R>, lds);
+  if (e != hipSuccess) return hip_check(nullptr, e, "k_spectra attribute");
+  hipLaunchKernelGGL(ns::k_spectra<R>, dim3(kSpecBlocks), dim3(64 * nwb), lds, stream, static_cast<const Cx<R>*>(u),
+                     static_cast<const Cx<R>*>(nh), nu, n, h, nsh, (long long)n * n * h, partials);
+  hipLaunchKernelGGL(ns::k_spectra_sum, dim3((nbins + 7) / 8), dim3(256), 0, stream, partials, kSpecBlocks, nbins,
+                     bins);
+  if ((st = hip_check(nullptr, hipGetLastError(), "spectra launch")) != NS_OK) return st;
+  double host[static_nbins(kStaticMaxN)];  // on the stack: no host allocation either
+  if ((st = hip_check(nullptr, hipMemcpyAsync(host, bins, set, hipMemcpyDeviceToHost, stream), "spectra copy")) !=
+      NS_OK)
+    return st;
+  if ((st = hip_check(nullptr, hipStreamSynchronize(stream), "spectra wait")) != NS_OK) return st;
+  if (out->e_shell) std::memcpy(out->e_shell, host, nsh * sizeof(double));
+  if (out->d_shell) std::memcpy(out->d_shell, host + nsh, nsh * sizeof(double));
+  if (out->t_shell) std::memcpy(out->t_shell, host + 2 * nsh, nsh * sizeof(double));
+  if (out->e_1d) std::memcpy(out->e_1d, host + 3 * nsh, 3 * h * sizeof(double));
+  if (out->totals) std::memcpy(out->totals, host + 3 * nsh + 3 * h, 5 * sizeof(double));
+  if (host[3 * nsh + 3 * h + 4] != 0.0) return fail(nullptr, NS_ERR_NONFINITE, "non-finite entries in input");
+  return NS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ns_status ns_spectra_static(int32_t n, int32_t precision, double nu, const void* u_hat, const void* n_hat,
+                            void* stream, ns_spectra_out* out) {
+  if (!factor_ok(n, nullptr)) return fail(nullptr, NS_ERR_ARG, "n must be 2^a 3^b 5^c with a >= 1 and 8 <= n <= 1024");
+  if (n > kStaticMaxN)
+    return fail(nullptr, NS_ERR_SIZE, "ns_spectra_static supports n <= " + std::to_string(kStaticMaxN) +
+                                          " (the size of its static scratch); use ns_spectra");
+  if (precision != NS_FP32 && precision != NS_FP64) return fail(nullptr, NS_ERR_ARG, "precision must be NS_FP32 or NS_FP64");
+  if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(nullptr, NS_ERR_ARG, "nu must be finite and >= 0");
+  if (!aligned(u_hat) || (n_hat != nullptr && !aligned(n_hat)))
+    return fail(nullptr, NS_ERR_ARG, "u_hat (and n_hat if given) must be 256-byte aligned device pointers");
+  if (!out) return fail(nullptr, NS_ERR_ARG, "out is NULL");
+  if (3 * num_shells(n) + 3 * (n / 2 + 1) + 5 > static_nbins(kStaticMaxN))
+    return fail(nullptr, NS_ERR_SIZE, "spectra bins exceed the static scratch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return precision == NS_FP32 ? spectra_static_t<float>(n, nu, u_hat, n_hat, s, out)
+                              : spectra_static_t<double>(n, nu, u_hat, n_hat, s, out);
 }
 
 ns_status ns_spectra(ns_ctx* ctx, const void* u_hat, const void* n_hat, ns_spectra_out* out) {

@@ -32,7 +32,7 @@ ABI_FUNCTIONS = ("ns_workspace_bytes", "ns_num_shells", "ns_retained_bound", "ns
                  "ns_last_error", "ns_set_stream", "ns_nonlinear", "ns_step_rk4_trunc",
                  "ns_step_rk2_phaseshift", "ns_spectra", "ns_vjp_rk2_phaseshift", "ns_timing_enable",
                  "ns_timing_read", "ns1d_nonlinear", "ns1d_step", "ns_spectra_async", "ns_spectra_wait",
-                 "ns_budget_start", "ns_budget_stop", "ns_budget_read")
+                 "ns_budget_start", "ns_budget_stop", "ns_budget_read", "ns_spectra_static")
 NS_BUDGET_LEN = 8
 BUDGET_NAMES = ("t", "E", "eps", "E0", "int_eps", "int_p", "p_last", "residual")
 PASS_NAMES = ("x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue", "x_forward_inverse")
@@ -89,6 +89,7 @@ def lib():
         "ns_budget_start": (I32, [P, P]),
         "ns_budget_stop": (I32, [P]),
         "ns_budget_read": (I32, [P, P]),
+        "ns_spectra_static": (I32, [I32, I32, D, P, P, P, ctypes.POINTER(NSSpectraOut)]),
         "ns_timing_enable": (I32, [P, I32]),
         "ns_timing_read": (I32, [P, P, P]),
         "ns_spectra_async": (I32, [P, P, P]),
@@ -294,6 +295,31 @@ class Solver:
         self._check(lib().ns_timing_read(self.ctx, ms.ctypes.data_as(ctypes.c_void_p),
                                          cnt.ctypes.data_as(ctypes.c_void_p)))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(PASS_NAMES)}
+
+
+def spectra_static(u, n, nu, n_hat=None, check_finite=True):
+    """ns_spectra_static: the spectra of u (a [3, N, N, N/2+1] complex64 or complex128 CUDA
+    tensor) without a context and without allocating, on torch's current stream."""
+    import torch
+    prec = NS_FP32 if u.dtype == torch.complex64 else NS_FP64
+    shape = (3, n, n, n // 2 + 1)
+    for t, name in ((u, "u"), (n_hat, "n_hat")):
+        if t is not None and (tuple(t.shape) != shape or not t.is_contiguous() or t.device.type != "cuda"
+                              or t.dtype != u.dtype):
+            raise ValueError(f"{name} must be a contiguous {u.dtype} CUDA tensor of shape {shape}")
+    nsh, h = num_shells(n), n // 2 + 1
+    out = {"e_shell": np.zeros(nsh), "d_shell": np.zeros(nsh), "t_shell": np.zeros(nsh),
+           "e_1d": np.zeros((3, h)), "totals": np.zeros(5)}
+    so = NSSpectraOut(*[out[k].ctypes.data_as(ctypes.c_void_p) for k in
+                        ("e_shell", "d_shell", "t_shell", "e_1d", "totals")])
+    st = lib().ns_spectra_static(int(n), prec, float(nu), ctypes.c_void_p(u.data_ptr()),
+                                 None if n_hat is None else ctypes.c_void_p(n_hat.data_ptr()),
+                                 ctypes.c_void_p(torch.cuda.current_stream(u.device).cuda_stream), ctypes.byref(so))
+    if st == NS_ERR_NONFINITE and not check_finite:
+        return out
+    if st != NS_OK:
+        raise NSError(st, lib().ns_last_error(None).decode())
+    return out
 
 
 # ---------------------------------------------------------------- the 1D model
