@@ -9,7 +9,13 @@ against a dealiased reference run.
 prints one JSON object: per run the grid, truncation, error index (percent),
 wall time and speedup over the reference (at equal dt, and under the paper's
 CFL protocol: CFL 0.4 for the RK2 schemes and 1.0 for RK4, dt proportional to
-the grid spacing; the eight-shift scheme is costed with the RK2 CFL number).
+the grid spacing; the eight-shift scheme is costed with the RK2 CFL number);
+and the run's dissipation diagnostics (Sec. "Numerical methods and overview",
+Sec. "3D flow: Taylor-Green vortices", Fig. 4): the largest dissipation eps_max
+and its time, the Kolmogorov length eta~ = (nu^3 / eps_max)^(1/4) and k_max eta~,
+and at the time of eps_max the nonlinear energy flux Pi(k) = sum_{k' > k} T(k')
+(T of the run's own dealiased nonlinear term) and the cumulative dissipation
+sum_{k' <= k} D(k') / eps, from the FP64 spectra of the library.
 """
 
 import argparse
@@ -81,16 +87,23 @@ def error_index(e1d, e1d_ref, kmax):
     return float(per_dir.mean()), per_dir.tolist()
 
 
-def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=2026, kmax=KMAX, mask="sphere"):
+def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=2026, kmax=KMAX, mask="sphere",
+                     diagnostics=None):
     """Time-step the Taylor-Green field to t_end; returns the sample times, the 1D
     spectra [samples, 3, kmax + 1] taken every `every` time units from t_start, and
-    the wall time of the whole run (stepping and sampling)."""
+    the wall time of the whole run (stepping and sampling).  With a dict as
+    `diagnostics`, it also receives the dissipation diagnostics of the run at the
+    sample of largest eps (dissipation_diagnostics)."""
     import torch
     s = ns.Solver(n, nu, ct, mask=mask, precision="fp32", seed=seed)
     u = s.to_device(inputs.taylor_green(n))
     nsteps = int(round(t_end / dt))
     first, stride = int(round(t_start / dt)), max(1, int(round(every / dt)))
-    times, spec = [], []
+    times, spec, eps = [], [], []
+    # with diagnostics: the state at every sample goes into one of two buffers; once
+    # the sample's eps is known (one sample later) the state of the largest eps is kept
+    bufs = [s.empty(), s.empty()] if diagnostics is not None else None
+    best = s.empty() if diagnostics is not None else None
 
     def advance(i, k):
         if scheme == "rk4":
@@ -99,6 +112,14 @@ def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=20
             s.step_ps(u, dt, k, "random", step0=i)
         else:
             s.step_ps(u, dt, k, scheme)
+
+    def collect():
+        sp = s.spectra_wait()
+        spec.append(sp["e_1d"][:, :kmax + 1].copy())
+        eps.append(float(sp["totals"][1]))
+        j = len(eps) - 1
+        if bufs is not None and eps[j] == max(eps):
+            best.copy_(bufs[j % 2])
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -111,17 +132,39 @@ def run_taylor_green(scheme, n, ct, t_start, t_end, every, nu=NU, dt=DT, seed=20
         advance(k, nxt - k)
         k = nxt
         if pending:
-            spec.append(s.spectra_wait()["e_1d"][:, :kmax + 1].copy())
+            collect()
             pending = False
         if k >= first and (k - first) % stride == 0:
             s.spectra_async(u)
+            if bufs is not None:
+                bufs[len(times) % 2].copy_(u)
             times.append(k * dt)
             pending = True
     if pending:
-        spec.append(s.spectra_wait()["e_1d"][:, :kmax + 1].copy())
+        collect()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if diagnostics is not None and eps:
+        jmax = int(np.argmax(eps))
+        diagnostics.update(dissipation_diagnostics(s, best, scheme, nu, ct * n / 2.0))
+        diagnostics["t_eps_max"] = float(times[jmax])
     return np.array(times), np.array(spec), wall
+
+
+def dissipation_diagnostics(s, u, scheme, nu, kmax):
+    """eps, eta~ = (nu^3 / eps)^(1/4) and k_max eta~ of the state u, the nonlinear
+    energy flux through each shell Pi(n) = sum_{n' > n} T(n') and the cumulative
+    dissipation C(n) = sum_{n' <= n} D(n') / eps (Fig. 4b), where T is the transfer of
+    the scheme's own dealiased nonlinear term (the two-shift average for the phase-shift
+    schemes, the truncated product otherwise) and D the dissipation spectrum."""
+    nh = s.nonlinear(u, ps_avg=scheme in ("random", "approx", "exact", "exact8", "euler_ps"))
+    sp = s.spectra(u, nh)
+    e = float(sp["totals"][1])
+    t = sp["t_shell"]
+    flux = np.concatenate([np.cumsum(t[::-1])[::-1][1:], [0.0]])
+    eta = (nu ** 3 / e) ** 0.25
+    return {"eps_max": e, "eta_tilde": eta, "kmax_eta": kmax * eta, "flux": flux.tolist(),
+            "cum_dissipation": (np.cumsum(sp["d_shell"]) / e).tolist(), "transfer_total": float(sp["totals"][3])}
 
 
 def compare(t_start, t_end, every, runs=None, log=sys.stderr, table=None, reference=REFERENCE, kmax=KMAX):
@@ -132,9 +175,11 @@ def compare(t_start, t_end, every, runs=None, log=sys.stderr, table=None, refere
     out = {}
     for name in runs:
         scheme, n, ct, _, mask = table[name]
-        tt, sp, wall = run_taylor_green(scheme, n, ct, t_start, t_end, every, mask=mask, kmax=kmax)
+        diag = {}
+        tt, sp, wall = run_taylor_green(scheme, n, ct, t_start, t_end, every, mask=mask, kmax=kmax,
+                                        diagnostics=diag)
         out[name] = {"scheme": scheme, "n": n, "ct": round(ct, 6), "mask": mask, "wall_s": wall, "times": tt,
-                     "spec": sp}
+                     "spec": sp, "diag": diag}
         print(f"[quality] {name}: {len(tt)} samples, {wall:.2f} s", file=log, flush=True)
     ref = out[reference]
     _, nr, _, cfl_r, _ = table[reference]
@@ -148,6 +193,12 @@ def compare(t_start, t_end, every, runs=None, log=sys.stderr, table=None, refere
                       "error_pct_xyz": [round(d, 4) for d in dirs], "wall_s": round(r["wall_s"], 4),
                       "speedup_equal_dt": round(eq, 3),
                       "speedup_cfl_protocol": round(eq * (cfl * nr) / (cfl_r * n), 3)}
+        d = r["diag"]
+        if d:
+            rows[name].update({"eps_max": round(d["eps_max"], 8), "t_eps_max": round(d["t_eps_max"], 4),
+                               "eta_tilde": round(d["eta_tilde"], 8), "kmax_eta": round(d["kmax_eta"], 4),
+                               "flux": [round(v, 8) for v in d["flux"][:kmax + 2]],
+                               "cum_dissipation": [round(v, 6) for v in d["cum_dissipation"][:kmax + 2]]})
     return rows
 
 

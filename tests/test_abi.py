@@ -142,3 +142,19 @@ def test_model1d_step_argument_errors(dt, nsteps, scheme):
     p = ctypes.c_void_p(256)
     assert L.ns1d_step(p, 16, 1.0, 1, dt, nsteps, scheme, None) == ns.NS_ERR_ARG
     assert L.ns1d_nonlinear(p, p, 16, 1.0, 1, float("inf"), None) == ns.NS_ERR_ARG
+
+
+def test_spectra_static_host_checks():
+    """ns_spectra_static rejects grids beyond its static scratch and bad arguments on the
+    host, before any HIP call."""
+    L = ns.lib()
+    out = ns.NSSpectraOut()
+    p = ctypes.c_void_p(256)
+    assert L.ns_spectra_static(768, ns.NS_FP32, 0.01, p, None, None, ctypes.byref(out)) == ns.NS_ERR_SIZE
+    assert b"512" in L.ns_last_error(None)
+    assert L.ns_spectra_static(7, ns.NS_FP32, 0.01, p, None, None, ctypes.byref(out)) == ns.NS_ERR_ARG
+    assert L.ns_spectra_static(64, 5, 0.01, p, None, None, ctypes.byref(out)) == ns.NS_ERR_ARG
+    assert L.ns_spectra_static(64, ns.NS_FP32, -1.0, p, None, None, ctypes.byref(out)) == ns.NS_ERR_ARG
+    assert L.ns_spectra_static(64, ns.NS_FP32, 0.01, ctypes.c_void_p(0x101), None, None,
+                               ctypes.byref(out)) == ns.NS_ERR_ARG
+    assert L.ns_spectra_static(64, ns.NS_FP32, 0.01, p, None, None, None) == ns.NS_ERR_ARG
