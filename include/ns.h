@@ -208,10 +208,14 @@ ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps,
  *           S = E_dt S0 + dt/2 E_{dt/2} (N(S0;alpha) + N(S1;beta) + 2 O)
  *   rk2:    the exact formula with A = N(.;0); exact8: with A the 8-shift average
  *   euler:  S = E_dt (S0 + dt A(S0)), A = N(.;0) or (euler_ps) the two-shift average
- * with E_tau = exp(-nu |k|^2 tau). */
+ * with E_tau = exp(-nu |k|^2 tau).
+ * stage1 (nullable; Heun variants with nsteps == 1): a state-layout device array,
+ * distinct from u_hat, that receives the step's first-stage state S1 on the
+ * retained modes (other entries are not written), for ns_vjp_rk2_phaseshift; the
+ * result in u_hat is the same bit for bit. */
 ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps,
                                  int32_t variant, const double* alphas,
-                                 const ns_forcing* forcing, int64_t step0);
+                                 const ns_forcing* forcing, int64_t step0, void* stage1);
 
 /* FP64 spectra and totals of the state u_hat (and the transfer with n_hat when
  * non-NULL), Sec. "3D flow: Taylor-Green vortices".  Every bin is summed in a
@@ -255,10 +259,14 @@ ns_status ns_spectra_wait(ns_ctx* ctx, ns_spectra_out* out);
  * forcing (nullable; Heun variants): the forward step was forced (Eq. forcing-eq)
  * with the draw of step `step`; it is redrawn from u_hat0, and the adjoint also
  * carries the dependence of the forcing amplitude on u_hat0 (a B + a^2 dt/2 G =
- * injection with B = <u_hat0, g>, so da/dB = -a / sqrt(B^2 + 2 dt G injection)). */
+ * injection with B = <u_hat0, g>, so da/dB = -a / sqrt(B^2 + 2 dt G injection)).
+ * stage1 (nullable; Heun variants): the first-stage state S1 of the forward step,
+ * as ns_step_rk2_phaseshift kept it; the adjoint then uses it instead of
+ * evaluating it again (one nonlinear-term evaluation less), with the same result
+ * bit for bit. */
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt,
                                 int32_t variant, const double alpha[3], const ns_forcing* forcing,
-                                int64_t step);
+                                int64_t step, const void* stage1);
 
 /* FP64 time-integrated energy budget on the GPU (Sec. "3D flow: Taylor-Green
  * vortices": dE/dt = -eps for the free flow; Sec. "Numerical methods": the forced

@@ -3,7 +3,9 @@ library's forward steps and its hand-written step adjoint (ns_vjp_rk2_phaseshift
 
 Forward keeps a copy of the state every `checkpoint_every` steps; backward walks
 the segments in reverse, recomputes the states of each segment from its
-checkpoint, and applies the step adjoints in reverse order.
+checkpoint (keeping each recomputed Heun step's first-stage state, which its
+adjoint then does not evaluate again), and applies the step adjoints in reverse
+order.
 
 Gradient convention: torch's gradient of a real loss with respect to a complex
 tensor is dL/dRe + i dL/dIm with every stored entry an independent variable.
@@ -57,18 +59,23 @@ class PSRK2Function(torch.autograd.Function):
         w = hermitian_weight(s.n, grad.device, real)
         lam = (grad / w).contiguous()
         nseg = len(ctx.ckpts)
+        heun = ctx.variant in ("approx", "random")
         for seg in reversed(range(nseg)):
             start = seg * every
             end = min(start + every, nsteps)
             states = [ctx.ckpts[seg]]
+            stage1 = []   # the first-stage states of the recomputed steps (Heun variants)
             u = ctx.ckpts[seg].clone()
             for i in range(start, end - 1):
+                s1 = s.empty() if heun else None
                 s.step_ps(u, dt, 1, ctx.variant, alphas=None if al is None else al[i:i + 1], forcing=ctx.forcing,
-                          step0=i)
+                          step0=i, stage1=s1)
                 states.append(u.clone())
+                stage1.append(s1)
+            stage1.append(None)   # the segment's last step is not recomputed: its adjoint evaluates S1
             for i in reversed(range(start, end)):
                 s.vjp_ps(states[i - start], lam, dt, ctx.variant, alpha=None if al is None else al[i],
-                         forcing=ctx.forcing, step=i)
+                         forcing=ctx.forcing, step=i, stage1=stage1[i - start])
         ctx.ckpts = None
         return lam * w, None, None, None, None, None, None, None
 

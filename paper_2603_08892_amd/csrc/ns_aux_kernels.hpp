@@ -326,37 +326,40 @@ k_forcing_adj_add(Cx<R>* __restrict__ lam, Lay ll, const ForceState* __restrict_
 // ------------------------------------------------------------------ energy budget
 // Pass 1: E = 1/2 sum w |u|^2 and eps = nu sum w |k|^2 |u|^2 over the retained
 // modes of a state (any layout; entries outside the retained set are ignored),
-// per block in a fixed order: a grid-stride loop over (row, k_z < kzn), a
-// shuffle tree per wavefront, the wavefronts in order.
-constexpr int kBudgetBlocks = 256;
+// per block in a fixed order: every wavefront takes whole (k_x, k_y) rows in a
+// grid-stride loop (rows whose k_z = 0 mode is not retained hold no retained mode
+// and are skipped), lanes along k_z < kzn; a shuffle tree per wavefront, then the
+// wavefronts in order.
+constexpr int kBudgetBlocks = 1024;
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_budget_partial(const Cx<R>* __restrict__ u, Lay lu, Geom g, double nu, double* __restrict__ partials) {
   __shared__ double we[4], wd[4];
-  const uint32_t n = (uint32_t)g.n, kzn = (uint32_t)g.kzn;
-  const uint32_t total = n * n * kzn;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nrows = g.n * g.n, nwaves = gridDim.x * 4;
   double e = 0.0, d = 0.0;
-  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < total; t += gridDim.x * 256u) {
-    const uint32_t row = t / kzn, kz = t - row * kzn;
-    const int xi = (int)(row / n), yi = (int)(row - (uint32_t)xi * n);
+  for (int row = blockIdx.x * 4 + wave; row < nrows; row += nwaves) {
+    const int xi = row / g.n, yi = row - xi * g.n;
     const int kx = kval(xi, g.n), ky = kval(yi, g.n);
-    if (!retained(g, kx, ky, (int)kz)) continue;
-    const long long idx = lay_at(lu, xi, yi, (int)kz, g.n);
-    const double w = (kz == 0 || 2 * (int)kz == g.n) ? 1.0 : 2.0;
-    double m2 = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      const Cx<R> a = u[c * lu.cs + idx];
-      m2 += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+    if (!retained(g, kx, ky, 0)) continue;  // the same for the whole wavefront
+    const long long base = lay_at(lu, xi, yi, 0, g.n);
+    for (int kz = lane; kz < g.kzn; kz += 64) {
+      if (!retained(g, kx, ky, kz)) continue;
+      const double w = (kz == 0 || 2 * kz == g.n) ? 1.0 : 2.0;
+      double m2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        const Cx<R> a = u[c * lu.cs + base + kz];
+        m2 += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+      }
+      const double em = 0.5 * w * m2;
+      e += em;
+      d += 2.0 * nu * (double)((long long)kx * kx + (long long)ky * ky + (long long)kz * kz) * em;
     }
-    const double em = 0.5 * w * m2;
-    e += em;
-    d += 2.0 * nu * (double)((long long)kx * kx + (long long)ky * ky + (long long)kz * kz) * em;
   }
   for (int off = 32; off > 0; off >>= 1) {
     e += __shfl_down(e, off);
     d += __shfl_down(d, off);
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     we[wave] = e;
     wd[wave] = d;

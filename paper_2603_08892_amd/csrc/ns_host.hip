@@ -397,7 +397,7 @@ double sm64_uniform_host(uint64_t seed, long long step, long long j) {
 
 template <typename R>
 ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const double* alphas,
-               const ns_forcing* fo, long long step0) {
+               const ns_forcing* fo, long long step0, void* stage1) {
   Cx<R>* s0 = static_cast<Cx<R>*>(u);
   Ptrs<R> p = ptrs<R>(c);
   const ns::Lay U = user_lay(c->lay), K = compact_lay(c->lay);
@@ -513,13 +513,21 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     a.li0 = lx;
     a.out0 = p.ab;
     a.out1 = p.sb;
+    // with stage1 the first-stage state is written to the caller's array (state
+    // layout, retained modes) and read back from there, not fed through registers
+    Cx<R>* s1 = stage1 ? static_cast<Cx<R>*>(stage1) : p.sb;
+    const ns::Lay l1 = stage1 ? U : K;
+    if (stage1) {
+      a.out1 = s1;
+      a.lo1 = U;
+    }
     if (fo != nullptr) {
       if ((st = forcing_draw<R>(c, x, lx, fo, step0 + i, dt)) != NS_OK) return st;
       a.force = p.force;
     }
     Chain ch;
     ch.front_done = fused;
-    ch.feed = 2;
+    ch.feed = stage1 ? 0 : 2;
     ch.next_s = be;
     if ((st = eval<R, ns::OP_HEUN1>(c, x, lx, al, a, &ch)) != NS_OK) return st;
     EpiArgs<R> f = epi<R>(c, fy);
@@ -530,7 +538,7 @@ ns_status ps_t(ns_ctx* c, void* u, double dt, int nsteps, int variant, const dou
     ch.front_done = ch.fused;
     ch.feed = last ? 0 : 1;
     ch.next_s = an;
-    if ((st = eval<R, ns::OP_HEUN2>(c, p.sb, K, be, f, &ch)) != NS_OK) return st;
+    if ((st = eval<R, ns::OP_HEUN2>(c, s1, l1, be, f, &ch)) != NS_OK) return st;
     fused = ch.fused;
     return NS_OK;
   };
@@ -600,7 +608,7 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
 
 template <typename R>
 ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, const double* alpha,
-                const ns_forcing* fo, long long step) {
+                const ns_forcing* fo, long long step, const void* stage1) {
   const Cx<R>* u0 = static_cast<const Cx<R>*>(u0v);
   Cx<R>* lam = static_cast<Cx<R>*>(lamv);
   Ptrs<R> p = ptrs<R>(c);
@@ -671,11 +679,20 @@ ns_status vjp_t(ns_ctx* c, const void* u0v, void* lamv, double dt, int variant, 
     if ((st = forcing_draw<R>(c, u0, U, fo, step, dt)) != NS_OK) return st;
     f.force = p.force;
   }
-  if ((st = eval<R, ns::OP_HEUN1>(c, u0, U, al, f)) != NS_OK) return st;  // sb = S1
+  // S1, the state the second stage is linearised at: the caller's (from the forward
+  // step) or recomputed here
+  const Cx<R>* s1 = p.sb;
+  ns::Lay l1s = K;
+  if (stage1 != nullptr) {
+    s1 = static_cast<const Cx<R>*>(stage1);
+    l1s = U;
+  } else if ((st = eval<R, ns::OP_HEUN1>(c, u0, U, al, f)) != NS_OK) {
+    return st;  // sb = S1
+  }
   LamArgs<R> l1 = lamargs(lam, U, R(0.5) * rdt, p.eh, nullptr, R(0), nullptr);
   AdjArgs<R> a = adj(0);
   a.out0 = p.ab;
-  if ((st = adj_eval<R, ns::AOP_STORE>(c, p.sb, K, be, l1, a)) != NS_OK) return st;  // ab = mu1
+  if ((st = adj_eval<R, ns::AOP_STORE>(c, s1, l1s, be, l1, a)) != NS_OK) return st;  // ab = mu1
   const Geom& g = c->lay.g;
   if (fo != nullptr) {
     // the amplitude's dependence on u0: (da/dB) <mu_O, g>, formed while lam is still the input
@@ -891,7 +908,7 @@ ns_status ns_step_rk4_trunc(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps,
 }
 
 ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t nsteps, int32_t variant,
-                                 const double* alphas, const ns_forcing* forcing, int64_t step0) {
+                                 const double* alphas, const ns_forcing* forcing, int64_t step0, void* stage1) {
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
   if (!aligned(u_hat)) return fail(ctx, NS_ERR_ARG, "u_hat must be a non-NULL 256-byte aligned device pointer");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NS_ERR_ARG, "dt must be finite and > 0");
@@ -904,10 +921,17 @@ ns_status ns_step_rk2_phaseshift(ns_ctx* ctx, void* u_hat, double dt, int32_t ns
   if (alphas && variant == NS_PS_RANDOM)
     for (int i = 0; i < 3 * nsteps; ++i)
       if (!std::isfinite(alphas[i])) return fail(ctx, NS_ERR_ARG, "alphas must be finite");
+  if (stage1 != nullptr) {
+    if (variant != NS_PS_APPROX && variant != NS_PS_RANDOM)
+      return fail(ctx, NS_ERR_ARG, "stage1 is kept by the Heun variants only");
+    if (nsteps != 1) return fail(ctx, NS_ERR_ARG, "stage1 needs nsteps == 1");
+    if (!aligned(stage1) || stage1 == u_hat)
+      return fail(ctx, NS_ERR_ARG, "stage1 must be a 256-byte aligned device array distinct from u_hat");
+  }
   if (nsteps == 0) return NS_OK;
   return ctx->cfg.precision == NS_FP32
-             ? ps_t<float>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0)
-             : ps_t<double>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0);
+             ? ps_t<float>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0, stage1)
+             : ps_t<double>(ctx, u_hat, dt, nsteps, variant, alphas, forcing, step0, stage1);
 }
 
 namespace {
@@ -1111,7 +1135,8 @@ ns_status ns_timing_read(ns_ctx* ctx, double* ms, int64_t* launches) {
 }
 
 ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, double dt, int32_t variant,
-                                const double alpha[3], const ns_forcing* forcing, int64_t step) {
+                                const double alpha[3], const ns_forcing* forcing, int64_t step,
+                                const void* stage1) {
   if (!ctx) return fail(nullptr, NS_ERR_ARG, "ctx is NULL");
   if (!aligned(u_hat0) || !aligned(lam)) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must be non-NULL 256-byte aligned device pointers");
   if (u_hat0 == lam) return fail(ctx, NS_ERR_ARG, "u_hat0 and lam must not overlap");
@@ -1125,8 +1150,12 @@ ns_status ns_vjp_rk2_phaseshift(ns_ctx* ctx, const void* u_hat0, void* lam, doub
   if (forcing && variant == NS_PS_EXACT) return fail(ctx, NS_ERR_ARG, "forcing is supported by the Heun variants only");
   ns_status st = check_forcing(ctx, forcing);
   if (st != NS_OK) return st;
-  return ctx->cfg.precision == NS_FP32 ? vjp_t<float>(ctx, u_hat0, lam, dt, variant, alpha, forcing, step)
-                                       : vjp_t<double>(ctx, u_hat0, lam, dt, variant, alpha, forcing, step);
+  if (stage1 != nullptr) {
+    if (variant == NS_PS_EXACT) return fail(ctx, NS_ERR_ARG, "stage1 is kept by the Heun variants only");
+    if (!aligned(stage1) || stage1 == lam) return fail(ctx, NS_ERR_ARG, "stage1 must be a 256-byte aligned device array distinct from lam");
+  }
+  return ctx->cfg.precision == NS_FP32 ? vjp_t<float>(ctx, u_hat0, lam, dt, variant, alpha, forcing, step, stage1)
+                                       : vjp_t<double>(ctx, u_hat0, lam, dt, variant, alpha, forcing, step, stage1);
 }
 
 ns_status ns_budget_start(ns_ctx* ctx, const void* u_hat) {

@@ -83,9 +83,9 @@ def lib():
         "ns_set_stream": (I32, [P, P]),
         "ns_nonlinear": (I32, [P, P, P, P, I32]),
         "ns_step_rk4_trunc": (I32, [P, P, D, I32, ctypes.POINTER(NSForcing), I64]),
-        "ns_step_rk2_phaseshift": (I32, [P, P, D, I32, I32, P, ctypes.POINTER(NSForcing), I64]),
+        "ns_step_rk2_phaseshift": (I32, [P, P, D, I32, I32, P, ctypes.POINTER(NSForcing), I64, P]),
         "ns_spectra": (I32, [P, P, P, ctypes.POINTER(NSSpectraOut)]),
-        "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P, ctypes.POINTER(NSForcing), I64]),
+        "ns_vjp_rk2_phaseshift": (I32, [P, P, P, D, I32, P, ctypes.POINTER(NSForcing), I64, P]),
         "ns_budget_start": (I32, [P, P]),
         "ns_budget_stop": (I32, [P]),
         "ns_budget_read": (I32, [P, P]),
@@ -212,12 +212,13 @@ class Solver:
                                             _forcing(forcing), int(step0)))
         return u
 
-    def step_ps(self, u, dt, nsteps=1, variant="random", alphas=None, forcing=None, step0=0):
+    def step_ps(self, u, dt, nsteps=1, variant="random", alphas=None, forcing=None, step0=0, stage1=None):
         """Steps in place of one of VARIANTS: the phase-shift RK2 schemes ("exact", "approx",
         "random"), midpoint RK2 and Euler without shifts ("rk2", "euler"), Euler with the
         two-shift average ("euler_ps") and the eight-shift exact RK2 ("exact8").
         alphas: array [nsteps, 3] (random variant) or None; forcing: dict(seed=...,
-        injection=1.0) or None (Heun variants only)."""
+        injection=1.0) or None (Heun variants only); stage1: a field tensor that receives
+        the first-stage state of a single Heun step (for vjp_ps)."""
         self._sync_stream()
         ap = None
         if alphas is not None:
@@ -226,7 +227,8 @@ class Solver:
                 raise ValueError("alphas must have shape [nsteps, 3]")
             ap = a.ctypes.data_as(ctypes.c_void_p)
         self._check(lib().ns_step_rk2_phaseshift(self.ctx, self._field(u, "u"), float(dt), int(nsteps),
-                                                 VARIANTS[variant], ap, _forcing(forcing), int(step0)))
+                                                 VARIANTS[variant], ap, _forcing(forcing), int(step0),
+                                                 None if stage1 is None else self._field(stage1, "stage1")))
         return u
 
     def _spectra_out(self):
@@ -260,13 +262,14 @@ class Solver:
         out, so = self._spectra_out()
         return self._spectra_status(lib().ns_spectra_wait(self.ctx, ctypes.byref(so)), out, check_finite)
 
-    def vjp_ps(self, u0, lam, dt, variant="random", alpha=None, forcing=None, step=0):
+    def vjp_ps(self, u0, lam, dt, variant="random", alpha=None, forcing=None, step=0, stage1=None):
         """In place: lam <- (dS_new/dS_0)^T lam for one phase-shift RK2 step at u0 (forced with
-        the draw of `step` when forcing is a dict(seed=..., injection=...))."""
+        the draw of `step` when forcing is a dict(seed=..., injection=...)); stage1: the
+        step's first-stage state kept by step_ps, which saves one evaluation."""
         self._sync_stream()
         self._check(lib().ns_vjp_rk2_phaseshift(self.ctx, self._field(u0, "u0"), self._field(lam, "lam"),
                                                 float(dt), VARIANTS[variant], _dbl3(alpha), _forcing(forcing),
-                                                int(step)))
+                                                int(step), None if stage1 is None else self._field(stage1, "stage1")))
         return lam
 
     def budget_start(self, u):

@@ -107,9 +107,9 @@ def test_null_context_rejected():
     L = ns.lib()
     assert L.ns_nonlinear(None, None, None, None, 0) == ns.NS_ERR_ARG
     assert L.ns_step_rk4_trunc(None, None, 0.1, 1, None, 0) == ns.NS_ERR_ARG
-    assert L.ns_step_rk2_phaseshift(None, None, 0.1, 1, 0, None, None, 0) == ns.NS_ERR_ARG
+    assert L.ns_step_rk2_phaseshift(None, None, 0.1, 1, 0, None, None, 0, None) == ns.NS_ERR_ARG
     assert L.ns_spectra(None, None, None, None) == ns.NS_ERR_ARG
-    assert L.ns_vjp_rk2_phaseshift(None, None, None, 0.1, 0, None, None, 0) == ns.NS_ERR_ARG
+    assert L.ns_vjp_rk2_phaseshift(None, None, None, 0.1, 0, None, None, 0, None) == ns.NS_ERR_ARG
     assert L.ns_budget_start(None, None) == ns.NS_ERR_ARG
     assert L.ns_budget_stop(None) == ns.NS_ERR_ARG
     assert L.ns_budget_read(None, None) == ns.NS_ERR_ARG

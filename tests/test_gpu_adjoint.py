@@ -160,3 +160,28 @@ def test_vjp_specialised_passes_match_generic(n, ct):
         gen.vjp_ps(gen.to_device(u0), b, dt, variant, alpha=al)
         ga, gb = _host(a), _host(b)
         assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) < 1e-5, variant
+
+
+@pytest.mark.parametrize("n,prec,forced", [(32, "fp32", False), (64, "fp32", True), (24, "fp64", True),
+                                           (128, "fp32", True)])
+def test_vjp_with_kept_first_stage_is_identical(n, prec, forced):
+    """A Heun step that keeps its first-stage state gives the same next state, and the
+    adjoint given that state the same result, bit for bit, as without it."""
+    import torch
+    nu, dt, ct = 0.02, 0.01, 1.0
+    print(f"[vjp stage1] n={n} {prec} forced={forced}", flush=True)
+    s = _solver(n, ct, prec, nu)
+    k2 = grid.sphere_k2max(n, ct)
+    u0 = _rep(inputs.hit_initial(n, 91, k2), prec)
+    lam = _rep(inputs.random_solenoidal(n, 92, k2), prec)
+    fo = {"seed": 13, "injection": 1.0} if forced else None
+    alpha = [(0.41, 0.07, 0.66)]
+    a, b = s.to_device(u0), s.to_device(u0)
+    s1 = s.empty()
+    s.step_ps(a, dt, 1, "random", alphas=alpha, forcing=fo, step0=5)
+    s.step_ps(b, dt, 1, "random", alphas=alpha, forcing=fo, step0=5, stage1=s1)
+    assert torch.equal(a, b)
+    la, lb = s.to_device(lam), s.to_device(lam)
+    s.vjp_ps(s.to_device(u0), la, dt, "random", alpha=alpha[0], forcing=fo, step=5)
+    s.vjp_ps(s.to_device(u0), lb, dt, "random", alpha=alpha[0], forcing=fo, step=5, stage1=s1)
+    assert torch.equal(la, lb)

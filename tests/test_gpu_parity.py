@@ -301,7 +301,7 @@ def test_zero_steps_and_argument_errors():
         with pytest.raises(ns.NSError):
             s.vjp_ps(ud, lam, 0.1, v)
     for bad in (-1, 7):
-        assert ns.lib().ns_step_rk2_phaseshift(s.ctx, s._field(ud, "u"), 0.1, 1, bad, None, None, 0) == ns.NS_ERR_ARG
+        assert ns.lib().ns_step_rk2_phaseshift(s.ctx, s._field(ud, "u"), 0.1, 1, bad, None, None, 0, None) == ns.NS_ERR_ARG
     assert np.array_equal(_host(ud), u)
     with pytest.raises(ns.NSError):
         s.nonlinear(ud, out=ud)
