@@ -164,8 +164,13 @@ __device__ __forceinline__ double sm64_uniform(uint64_t seed, long long step, lo
 }
 
 // Forced modes 4 <= |k|^2 <= 9 in draw order (k_z 0..3, then k_x, k_y from -3 to 3;
-// on k_z = 0 only k_x > 0, or k_x = 0 and k_y > 0): 48 independent modes.
-__device__ __forceinline__ int forcing_mode(int i, int* kx, int* ky, int* kz) {
+// on k_z = 0 only k_x > 0, or k_x = 0 and k_y > 0): 48 independent modes, listed at
+// compile time.
+struct ForcingModes {
+  int k[48][3];
+};
+constexpr ForcingModes make_forcing_modes() {
+  ForcingModes m{};
   int c = 0;
   for (int z = 0; z <= 3; ++z)
     for (int x = -3; x <= 3; ++x)
@@ -173,36 +178,52 @@ __device__ __forceinline__ int forcing_mode(int i, int* kx, int* ky, int* kz) {
         const int k2 = x * x + y * y + z * z;
         if (k2 < 4 || k2 > 9) continue;
         if (z == 0 && !(x > 0 || (x == 0 && y > 0))) continue;
-        if (c == i) { *kx = x; *ky = y; *kz = z; return 1; }
+        m.k[c][0] = x;
+        m.k[c][1] = y;
+        m.k[c][2] = z;
         ++c;
       }
-  return 0;
+  return m;
+}
+__device__ __forceinline__ void forcing_mode(int i, int* kx, int* ky, int* kz) {
+  constexpr ForcingModes m = make_forcing_modes();
+  static_assert(m.k[47][2] == 3 && m.k[0][2] == 0, "48 forced modes");
+  *kx = m.k[i][0];
+  *ky = m.k[i][1];
+  *kz = m.k[i][2];
 }
 
-// One block of 64 threads: draw g for `step`, project it, scale it to inject
-// energy at rate `inj` over a step dt from state u, write the dense table
-// force[c][k_x+3][k_y+3][k_z] (k_z <= 3) and the FP64 record fs.
+// One block of 192 threads: draw g for `step` (thread 3 i + c the Gaussian pair of
+// mode i, component c), project it, scale it to inject energy at rate `inj` over a
+// step dt from state u, write the dense table force[c][k_x+3][k_y+3][k_z] (k_z <= 3)
+// and the FP64 record fs.
 template <typename R>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(192)
 k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, ForceState* __restrict__ fs, int n,
           int pitch, long long comp, uint64_t seed, long long step, double dt, double inj) {
   __shared__ double gre[48][3], gim[48][3], pb[48], pg[48];
   __shared__ double amp;
-  const int i = threadIdx.x;
-  for (int t = i; t < 3 * 196; t += blockDim.x) force[t] = cx(R(0), R(0));
-  if (i < 48) {
+  const int q = threadIdx.x;
+  for (int t = q; t < 3 * 196; t += blockDim.x) force[t] = cx(R(0), R(0));
+  if (q < 144) {
+    const long long p = q;  // = 3 i + c
+    const double u1 = sm64_uniform(seed, step, 2 * p);
+    const double u2 = sm64_uniform(seed, step, 2 * p + 1);
+    const double r = sqrt(-2.0 * log(1.0 - u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    gre[q / 3][q % 3] = r * cs;
+    gim[q / 3][q % 3] = r * sn;
+  }
+  __syncthreads();
+  if (q < 48) {
+    const int i = q;
     int kx, ky, kz;
     forcing_mode(i, &kx, &ky, &kz);
     double vr[3], vi[3];
     for (int c = 0; c < 3; ++c) {
-      const long long p = 3 * i + c;
-      const double u1 = sm64_uniform(seed, step, 2 * p);
-      const double u2 = sm64_uniform(seed, step, 2 * p + 1);
-      const double r = sqrt(-2.0 * log(1.0 - u1));
-      double sn, cs;
-      sincospi(2.0 * u2, &sn, &cs);
-      vr[c] = r * cs;
-      vi[c] = r * sn;
+      vr[c] = gre[i][c];
+      vi[c] = gim[i][c];
     }
     const double k2 = (double)(kx * kx + ky * ky + kz * kz);
     const double dr = (kx * vr[0] + ky * vr[1] + kz * vr[2]) / k2;
@@ -226,12 +247,17 @@ k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, ForceState* __
         g2 += vr[c] * vr[c] + vi[c] * vi[c];
       }
     }
-    for (int c = 0; c < 3; ++c) { gre[i][c] = vr[c]; gim[i][c] = vi[c]; }
+    for (int c = 0; c < 3; ++c) {
+      gre[i][c] = vr[c];
+      gim[i][c] = vi[c];
+      fs->g[i][c][0] = vr[c];
+      fs->g[i][c][1] = vi[c];
+    }
     pb[i] = b;
     pg[i] = g2;
   }
   __syncthreads();
-  if (i == 0) {
+  if (q == 0) {
     double B = 0, G = 0;
     for (int m = 0; m < 48; ++m) { B += pb[m]; G += pg[m]; }
     const double r = sqrt(B * B + 2.0 * dt * G * inj);
@@ -243,18 +269,13 @@ k_forcing(const Cx<R>* __restrict__ u, Cx<R>* __restrict__ force, ForceState* __
     fs->injected = dt * (amp * B + 0.5 * amp * amp * dt * G);
   }
   __syncthreads();
-  if (i < 48) {
+  if (q < 144) {
+    const int i = q / 3, c = q % 3;
     int kx, ky, kz;
     forcing_mode(i, &kx, &ky, &kz);
-    for (int c = 0; c < 3; ++c) {
-      fs->g[i][c][0] = gre[i][c];
-      fs->g[i][c][1] = gim[i][c];
-    }
-    for (int c = 0; c < 3; ++c) {
-      const double re = amp * gre[i][c], im = amp * gim[i][c];
-      force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz] = cx(R(re), R(im));
-      if (kz == 0) force[c * 196 + ((-kx + 3) * 7 + (-ky + 3)) * 4] = cx(R(re), R(-im));
-    }
+    const double re = amp * gre[i][c], im = amp * gim[i][c];
+    force[c * 196 + ((kx + 3) * 7 + (ky + 3)) * 4 + kz] = cx(R(re), R(im));
+    if (kz == 0) force[c * 196 + ((-kx + 3) * 7 + (-ky + 3)) * 4] = cx(R(re), R(-im));
   }
 }
 

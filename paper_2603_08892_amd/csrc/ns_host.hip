@@ -312,7 +312,7 @@ ns_status etab(ns_ctx* c, double dt) {
 template <typename R>
 ns_status forcing_draw(ns_ctx* c, const Cx<R>* x, ns::Lay lx, const ns_forcing* fo, long long step, double dt) {
   Ptrs<R> p = ptrs<R>(c);
-  hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(64), 0, c->stream, x, p.force, p.fstate, c->lay.g.n, lx.pitch,
+  hipLaunchKernelGGL(ns::k_forcing<R>, dim3(1), dim3(192), 0, c->stream, x, p.force, p.fstate, c->lay.g.n, lx.pitch,
                      lx.cs, fo->seed, step, dt, fo->injection);
   return hip_check(c, hipGetLastError(), "k_forcing launch");
 }

@@ -120,8 +120,6 @@ def test_autograd_checkpointed_gradient(prec):
 def test_vjp_specialised_passes_match_oracle(n, ct, mask, variant):
     """The specialised FP32 adjoint passes (N = 64, 128) against the FP64 oracle's adjoint."""
     from paper_2603_08892_amd import ns
-    if n == 128 and variant == "approx":
-        pytest.skip("one Heun variant at 128^3 is enough (the oracle adjoint takes seconds)")
     print(f"[vjp fast] n={n} ct={ct:.3f} {mask} {variant}", flush=True)
     nu, dt = 0.02, 0.01
     s = ns.Solver(n, nu, ct, mask=mask, precision="fp32", seed=5)

@@ -42,6 +42,11 @@ def _host(t):
 def _check(got, want, prec, what=""):
     l2 = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
     mx = np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
+    aw = np.abs(want)
+    big = aw > 1e-3 * aw.max()
+    per_mode = float((np.abs(got - want)[big] / aw[big]).max()) if big.any() else 0.0
+    print(f"[parity] {what} {got.shape[-2]}^3 {prec}: rel L2 {l2:.2e} max/max {mx:.2e} "
+          f"per-mode (>1e-3 max) {per_mode:.2e}", flush=True)
     tl2, tmx = TOL[prec]
     assert l2 <= tl2 and mx <= tmx, f"{what}: rel L2 {l2:.3e} rel max {mx:.3e}"
 
