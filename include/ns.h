@@ -113,8 +113,9 @@ typedef struct {
 } ns_config;
 
 /* Config flag: always use the size-generic passes (runtime radix plan) instead of
- * the compile-time specialised FP32 passes for N = 64, 128, 192, 216, 256, 324, 384, 512.  Results
- * agree to FP32 round-off; meant for testing and comparison. */
+ * the compile-time specialised FP32 passes for N = 64, 128, 144, 160, 192, 216, 240,
+ * 256, 270, 324, 360, 384, 512.  Results agree to FP32 round-off; meant for testing
+ * and comparison. */
 #define NS_CFG_GENERIC_PASSES 1
 
 /* Forcing of the "split" phase-shift scheme (Eq. forcing-eq) and of the RK4

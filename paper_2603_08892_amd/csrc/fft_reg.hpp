@@ -10,7 +10,14 @@
 // inputs of its first stage of a transform whose radix list starts with
 // R_last, so an inverse transform can feed a forward one without an exchange.
 //
-// Composite DFTs (6, 10, 12, 16, 24, 32) use the Cooley-Tukey split with
+// A stage of radix R has N/R butterflies; thread t takes butterflies
+// t + TPL b, b < ceil(N / (R TPL)), and where TPL does not divide N/R the last ones
+// are predicated off (a plan whose radices do not all divide one points-per-thread
+// count, e.g. 240 = 10 4 6 over 24 threads).  EPT is then the most points a thread
+// holds in any stage, and the first and last stages say which of its registers hold
+// points (in_ok, out_ok).
+//
+// Composite DFTs (6, 9, 10, 12, 16, 24, 32) use the Cooley-Tukey split with
 // compile-time twiddles; their cos/sin are evaluated at compile time from the
 // Taylor series of the reduced angle.
 #pragma once
@@ -125,6 +132,7 @@ __device__ __forceinline__ void rdft(Cx<T>* a) {
   else if constexpr (R == 5) dft5<S>(a);
   else if constexpr (R == 8) dft8<S>(a);
   else if constexpr (R == 6) rdft_split<2, 3, S>(a);
+  else if constexpr (R == 9) rdft_split<3, 3, S>(a);
   else if constexpr (R == 10) rdft_split<2, 5, S>(a);
   else if constexpr (R == 12) rdft_split<4, 3, S>(a);
   else if constexpr (R == 16) rdft_split<4, 4, S>(a);
@@ -167,15 +175,23 @@ __device__ __forceinline__ void exchange_barrier() {
   }
 }
 
+// Butterflies per thread of a stage of radix R, and whether all of them are real.
+template <int N, int TPL, int R>
+struct StageMap {
+  static constexpr int NB = (N / R + TPL - 1) / TPL;
+  static constexpr bool FULL = (N / R) % TPL == 0;
+  __device__ __forceinline__ static bool ok(int t, int b) { return FULL || t + TPL * b < N / R; }
+};
+
 template <int N, int TPL, int S, int NS, int R, int... Rest>
 struct RegStages {
   template <bool WAVE, typename T, int ES>
   __device__ __forceinline__ static void run(Cx<T>* v, int t, const LineView<T, ES>& lv, const Cx<T>* tw) {
-    constexpr int EPT = N / TPL;
-    constexpr int NB = EPT / R;
-    static_assert(EPT % R == 0, "radix must divide the points per thread");
+    using M = StageMap<N, TPL, R>;
+    constexpr int NB = M::NB;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
+      if (!M::ok(t, b)) continue;
       const int j = t + TPL * b;
       if constexpr (NS > 1) {
         const int k = j % NS;
@@ -189,10 +205,12 @@ struct RegStages {
     }
     if constexpr (sizeof...(Rest) > 0) {
       constexpr int R2 = first_of<Rest...>();
-      constexpr int NB2 = EPT / R2;
+      using M2 = StageMap<N, TPL, R2>;
+      constexpr int NB2 = M2::NB;
       exchange_barrier<WAVE>();
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
+        if (!M::ok(t, b)) continue;
         const int j = t + TPL * b;
         const int k = j % NS, q = j / NS;
 #pragma unroll
@@ -201,6 +219,7 @@ struct RegStages {
       exchange_barrier<WAVE>();
 #pragma unroll
       for (int b = 0; b < NB2; ++b) {
+        if (!M2::ok(t, b)) continue;
         const int j = t + TPL * b;
 #pragma unroll
         for (int m = 0; m < R2; ++m) v[b * R2 + m] = lv.at(j + m * (N / R2));
@@ -215,6 +234,23 @@ struct RegStages {
 template <int... Rs>
 struct Radices {
   static constexpr int count = sizeof...(Rs);
+  // most points a thread holds in any stage of an N-point transform over TPL threads
+  template <int N, int TPL>
+  static constexpr int ept() {
+    int e = 0;
+    for (int r : {Rs...}) {
+      const int v = (N / r + TPL - 1) / TPL * r;
+      e = v > e ? v : e;
+    }
+    return e;
+  }
+  // every stage gives every thread the same number of whole butterflies
+  template <int N, int TPL>
+  static constexpr bool uniform() {
+    bool u = true;
+    for (int r : {Rs...}) u = u && (N / r) % TPL == 0 && (N / r) / TPL * r == N / TPL;
+    return u;
+  }
   static constexpr int first() { return first_impl<Rs...>(); }
   static constexpr int last() { return last_impl<Rs...>(); }
   static constexpr int product() { return (Rs * ...); }
@@ -232,7 +268,8 @@ struct RegFft;
 template <int N, int TPL, int S, int... Rs>
 struct RegFft<N, TPL, S, Radices<Rs...>> {
   using Rad = Radices<Rs...>;
-  static constexpr int EPT = N / TPL;
+  static constexpr int EPT = Rad::template ept<N, TPL>();
+  static constexpr bool UNIFORM = Rad::template uniform<N, TPL>();
   static constexpr int R0 = Rad::first();
   static constexpr int RL = Rad::last();
   static_assert(Rad::product() == N, "radices must multiply to N");
@@ -240,6 +277,21 @@ struct RegFft<N, TPL, S, Radices<Rs...>> {
   __device__ __forceinline__ static int in_pos(int t, int i) { return t + TPL * (i / R0) + (i % R0) * (N / R0); }
   // output position of register i (i = b * RL + m) of thread t after the last stage
   __device__ __forceinline__ static int out_pos(int t, int i) { return t + TPL * (i / RL) + (i % RL) * (N / RL); }
+  // whether register i of thread t holds a point before the first / after the last
+  // stage (always, for a uniform plan); the positions of other registers are not
+  // points of the line and must not address memory
+  __device__ __forceinline__ static bool in_ok(int t, int i) {
+    if constexpr (UNIFORM) return true;
+    else return i / R0 < StageMap<N, TPL, R0>::NB && StageMap<N, TPL, R0>::ok(t, i / R0);
+  }
+  __device__ __forceinline__ static bool out_ok(int t, int i) {
+    if constexpr (UNIFORM) return true;
+    else return i / RL < StageMap<N, TPL, RL>::NB && StageMap<N, TPL, RL>::ok(t, i / RL);
+  }
+  // the positions with a stand-in 0 for registers that hold no point, for indexing
+  // tables of the line (the value of such a register is never used)
+  __device__ __forceinline__ static int in_at(int t, int i) { return in_ok(t, i) ? in_pos(t, i) : 0; }
+  __device__ __forceinline__ static int out_at(int t, int i) { return out_ok(t, i) ? out_pos(t, i) : 0; }
   template <bool WAVE = false, typename T, int ES>
   __device__ __forceinline__ static void run(Cx<T>* v, int t, const LineView<T, ES>& lv, const Cx<T>* tw) {
     static_assert(!WAVE || TPL <= 64, "a wavefront-local line fits in one wavefront");

@@ -11,7 +11,7 @@
 // spread banks) and the twiddle table.
 // Contiguous pass (z): a block holds P lines, thread (p, t) = (tid div TPL, tid mod TPL);
 // a line's threads synchronise at wavefront scope when TPL divides 64 and with
-// block barriers otherwise (N = 216, 324).
+// block barriers otherwise (N = 144, 216, 240, 270, 324, 360).
 // In the step sequences the x-forward kernel can also run the next evaluation's
 // x-inverse pass on its tile (template argument FEED), so a chained evaluation is
 // four launches: y-inverse, z, y-forward, x-forward (+ next x-inverse).
@@ -82,7 +82,8 @@ template <int N_, int TPL_, typename Inv_, typename Fwd_>
 struct LinePlan {
   static constexpr int N = N_;
   static constexpr int TPL = TPL_;
-  static constexpr int EPT = N_ / TPL_;
+  static constexpr int EPT = Inv_::template ept<N_, TPL_>();
+  static_assert(EPT == Fwd_::template ept<N_, TPL_>(), "both directions hold the same registers");
   using Inv = Inv_;   // radices of the inverse transforms
   using Fwd = Fwd_;   // radices of the forward transforms (reverse order of Inv)
 };
@@ -93,6 +94,7 @@ struct FastCfg {
   static constexpr int N = XI::N;
   static_assert(8ull * N * N * (N / 2 + 1) < (1ull << 32), "32-bit byte offsets need 8 N^2 (N/2+1) < 2^32");
   static constexpr int PZ = PZ_;
+  static_assert(N * N % PZ_ == 0, "the z pass runs N^2 / PZ blocks of PZ whole lines");
   using XInv = XI;
   using Y = YP;
   using Z = ZP;
@@ -140,8 +142,8 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
     const LineTest keep = line_test(g, ky, kz);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int p = F::in_pos(t, i);
-      ok[i] = col && keep(kval(p, N));
+      const int p = F::in_at(t, i);
+      ok[i] = col && F::in_ok(t, i) && keep(kval(p, N));
       idx[i] = (uint32_t)p * sstep + sbase;
     }
 #pragma unroll
@@ -153,7 +155,7 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int p = F::in_pos(t, i);
+    const int p = F::in_at(t, i);
     if (sh.on) {
       const Cx<float> phi = cmul(phx[p], phyz);
       ux[i] = cmul(ux[i], phi);
@@ -168,7 +170,8 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   auto store = [&](int f, const Cx<float>* v) {
     if (col) {
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) st_off(W + f * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
+      for (int i = 0; i < EPT; ++i)
+        if (F::out_ok(t, i)) st_off(W + f * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
     }
   };
   F::run(uy, t, lv, tw);
@@ -213,15 +216,15 @@ f_ypass(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, G
   Cx<float> v[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int p = F::in_pos(t, i);
-    v[i] = ld_masked(base, (uint32_t)(p * g.kzp) + rbase, col && (S < 0 || abs(kval(p, N)) <= yb));
+    const int p = F::in_at(t, i);
+    v[i] = ld_masked(base, (uint32_t)(p * g.kzp) + rbase, col && F::in_ok(t, i) && (S < 0 || abs(kval(p, N)) <= yb));
   }
   F::run(v, t, lv, tw);
   if (col) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int p = F::out_pos(t, i);
-      if (S > 0 || abs(kval(p, N)) <= yb) st_off(base, (uint32_t)(p * g.kzp) + rbase, v[i]);
+      if (F::out_ok(t, i) && (S > 0 || abs(kval(p, N)) <= yb)) st_off(base, (uint32_t)(p * g.kzp) + rbase, v[i]);
     }
   }
 }
@@ -263,7 +266,7 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   auto fetch = [&](int q, Cx<float>* a, Cx<float>* b) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int pos = FI::in_pos(t, i);
+      const int pos = FI::in_at(t, i);
       const int k = pos <= HN ? pos : N - pos;
       a[i] = ld_masked(W + (2 * q) * g.wcomp, lbase + k, k < g.kzn);
       b[i] = ld_masked(W + (2 * q + 1) * g.wcomp, lbase + k, k < g.kzn);
@@ -275,7 +278,7 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   for (int q = 0; q < 3; ++q) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int pos = FI::in_pos(t, i);
+      const int pos = FI::in_at(t, i);
       const Cx<float> a = ra[q & 1][i], bb = rb[q & 1][i];
       if (pos == 0 || pos == HN) v[i] = cx(a.re, bb.re);
       else if (pos < HN) v[i] = cx(a.re - bb.im, a.im + bb.re);
@@ -300,13 +303,15 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   for (int i = 0; i < EPT; ++i) v[i] = cx(fx[i], fy[i]);
   FF::template run<WV>(v, t, lv, tw);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) sp[p * N + FF::out_pos(t, i)] = v[i];
+  for (int i = 0; i < EPT; ++i)
+    if (FF::out_ok(t, i)) sp[p * N + FF::out_pos(t, i)] = v[i];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) v[i] = cx(fz[i], 0.f);
   FF::template run<WV>(v, t, lv, tw);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) xb[p * LP + FF::out_pos(t, i)] = v[i];
+  for (int i = 0; i < EPT; ++i)
+    if (FF::out_ok(t, i)) xb[p * LP + FF::out_pos(t, i)] = v[i];
   __syncthreads();
   for (int idx = tid; idx < P * g.kzn; idx += NT) {
     const int k = idx % g.kzn, pp = idx / g.kzn;
@@ -378,15 +383,16 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
 #pragma unroll
       for (int i = 0; i < EPT; ++i) nx[c][i] = cx(0.f, 0.f);
   }
-  constexpr int CH = ((need0 && need1) || ((need0 || need1) && N <= 128)) ? EPT / 2 : EPT;
+  constexpr int CH = ((need0 && need1) || ((need0 || need1) && N <= 128)) ? (EPT + 1) / 2 : EPT;
   const LineTest keep = line_test(g, ky, kz);
   const bool line_kept = active && kz < g.kzn;
   Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];
   auto load_ops = [&](int c0) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-      const int p = F::out_pos(t, c0 + j);
-      const bool ok = line_kept && keep(kval(p, N));
+      if (c0 + j >= EPT) break;  // an odd register count: the second chunk is one short
+      const int p = F::out_at(t, c0 + j);
+      const bool ok = line_kept && F::out_ok(t, c0 + j) && keep(kval(p, N));
       if constexpr (need0) {
         const uint32_t ii0 = (uint32_t)((p * N + yi) * a.li0.pitch + kz);
 #pragma unroll
@@ -415,13 +421,13 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
     const uint32_t wbase = (uint32_t)(yi * g.kzp + kz0) + l, wstep = (uint32_t)(N * g.kzp);
     // field f + 1 is loaded while field f is transformed
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) r[0][i] = ld_masked(W, (uint32_t)F::in_pos(t, i) * wstep + wbase, col);
+    for (int i = 0; i < EPT; ++i) r[0][i] = ld_masked(W, (uint32_t)F::in_at(t, i) * wstep + wbase, col && F::in_ok(t, i));
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       if (f < 2) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
-          r[f + 1][i] = ld_masked(W + (f + 1) * g.wcomp, (uint32_t)F::in_pos(t, i) * wstep + wbase, col);
+          r[f + 1][i] = ld_masked(W + (f + 1) * g.wcomp, (uint32_t)F::in_at(t, i) * wstep + wbase, col && F::in_ok(t, i));
       } else {
         load_ops(0);
       }
@@ -439,6 +445,8 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int i = c0 + j;
+    if (i >= EPT) break;
+    if (!F::out_ok(t, i)) continue;  // no point in this register
     const int p = F::out_pos(t, i);
     const int kx = kval(p, N);
     const uint32_t io0 = (uint32_t)((p * N + yi) * a.lo0.pitch + kz);
@@ -534,7 +542,7 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
     const Cx<float> phyz2 = sh2.on ? phc2[l] : cx(1.f, 0.f);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int p = FI::in_pos(t, i);
+      const int p = FI::in_at(t, i);
       ux[i] = nx[0][i];
       uy[i] = nx[1][i];
       uz[i] = nx[2][i];
@@ -553,7 +561,8 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
     auto store = [&](int f, const Cx<float>* v) {
       if (col) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) st_off(W + f * g.wcomp, (uint32_t)FI::out_pos(t, i) * ostep + obase, v[i]);
+        for (int i = 0; i < EPT; ++i)
+          if (FI::out_ok(t, i)) st_off(W + f * g.wcomp, (uint32_t)FI::out_pos(t, i) * ostep + obase, v[i]);
       }
     };
     FI::run(uy, t, lv, tw);
@@ -603,5 +612,24 @@ using Fast384 = FastCfg<LP384, LP384, LP384, 4, LP384>;
 using LP512 = LinePlan<512, 64, Radices<8, 8, 8>, Radices<8, 8, 8>>;
 using LP512x = LinePlan<512, 32, Radices<16, 8, 4>, Radices<4, 8, 16>>;
 using Fast512 = FastCfg<LP512x, LP512, LP512, 4, LP512x>;
+// Grids whose radices do not all divide one points-per-thread count: 12 registers
+// a thread, some butterflies of a stage predicated off (fft_reg.hpp).  144 = 12 12
+// (uniform, 12 threads), 160 = 10 4 4 (16), 240 = 10 4 6 (24), 270 = 9 6 5 (30),
+// 360 = 10 6 6 (36, the y and z passes): the truncation sweeps at k_max = 64 and 108 and the coarse
+// grid of the 512^3 comparison at C_t = 0.948.
+using LP144 = LinePlan<144, 12, Radices<12, 12>, Radices<12, 12>>;
+using LP160 = LinePlan<160, 16, Radices<10, 4, 4>, Radices<4, 4, 10>>;
+using LP240 = LinePlan<240, 24, Radices<10, 4, 6>, Radices<6, 4, 10>>;
+using LP270 = LinePlan<270, 30, Radices<9, 6, 5>, Radices<5, 6, 9>>;
+using LP360 = LinePlan<360, 36, Radices<10, 6, 6>, Radices<6, 6, 10>>;
+// x passes of 360: 30 threads per line (12 6 5, up to 15 registers a transform), so
+// that a 16-column tile is a 480-thread block that may hold 256 registers a thread
+// (576 threads allow 168, and the x-forward passes spilled)
+using LP360x = LinePlan<360, 30, Radices<12, 6, 5>, Radices<5, 6, 12>>;
+using Fast144 = FastCfg<LP144, LP144, LP144, 8, LP144>;
+using Fast160 = FastCfg<LP160, LP160, LP160, 8, LP160>;
+using Fast240 = FastCfg<LP240, LP240, LP240, 8, LP240>;
+using Fast270 = FastCfg<LP270, LP270, LP270, 4, LP270>;  // 270^2 is not a multiple of 8
+using Fast360 = FastCfg<LP360x, LP360, LP360, 8, LP360x>;
 
 }  // namespace ns

@@ -45,9 +45,9 @@ f_xlam(LamArgs<float> la, Cx<float>* __restrict__ W, const Cx<float>* __restrict
   Cx<float> q[3][EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int p = F::in_pos(t, i);
+    const int p = F::in_at(t, i);
     const int kx = kval(p, N);
-    const bool ok = col && keep(kx);
+    const bool ok = col && F::in_ok(t, i) && keep(kx);
     const int k2 = ok ? kx * kx + ky * ky + kz * kz : 0;
     const float fa = la.cA * (la.eA ? la.eA[k2] : 1.f);
     const uint32_t ia = (uint32_t)((p * N + yi) * la.la.pitch + kz);
@@ -82,7 +82,7 @@ f_xlam(LamArgs<float> la, Cx<float>* __restrict__ W, const Cx<float>* __restrict
     if (col) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i)
-        st_off(W + (6 + f) * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, q[f][i]);
+        if (F::out_ok(t, i)) st_off(W + (6 + f) * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, q[f][i]);
     }
   }
 }
@@ -118,7 +118,7 @@ f_zadj(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
   for (int q = 0; q < 5; ++q) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int pos = FI::in_pos(t, i);
+      const int pos = FI::in_at(t, i);
       const int k = pos <= HN ? pos : N - pos;
       const Cx<float> a = ld_masked(W + (2 * q) * g.wcomp, lbase + k, k < g.kzn);
       const Cx<float> bb = q < 4 ? ld_masked(W + (2 * q + 1) * g.wcomp, lbase + k, k < g.kzn) : cx(0.f, 0.f);
@@ -155,7 +155,8 @@ f_zadj(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
     FF::template run<WV>(v, t, lv, tw);
     exchange_barrier<WV>();  // the previous slice's split has read sp
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) sp[p * N + FF::out_pos(t, i)] = v[i];
+    for (int i = 0; i < EPT; ++i)
+      if (FF::out_ok(t, i)) sp[p * N + FF::out_pos(t, i)] = v[i];
     exchange_barrier<WV>();
     for (int k = t; k < g.kzn; k += TPL) {
       const Cx<float> c1 = sp[p * N + k], c2 = sp[p * N + ((N - k) % N)];
@@ -211,12 +212,12 @@ f_xadj(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
       Cx<float>* dst = f < 3 ? r[f] : v;
 #pragma unroll
       for (int i = 0; i < EPT; ++i)
-        dst[i] = ld_masked(W + f * g.wcomp, (uint32_t)F::in_pos(t, i) * wstep + wbase, col);
+        dst[i] = ld_masked(W + f * g.wcomp, (uint32_t)F::in_at(t, i) * wstep + wbase, col && F::in_ok(t, i));
       F::run(dst, t, lv, tw);  // its barriers also publish phx and phc
       if (f >= 3) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-          const float kxf = float(kval(F::out_pos(t, i), N));
+          const float kxf = float(kval(F::out_at(t, i), N));
           const Cx<float> iv = mul_i(v[i]);
           if (f == 3) {         // i k x (g2x, 0, 0) = (0, i kz g2x, -i ky g2x)
             r[1][i] = r[1][i] + scale(iv, kzf);
@@ -239,6 +240,7 @@ f_xadj(const Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift
   const float inv_n3 = 1.f / (float(N) * float(N) * float(N));
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
+    if (!F::out_ok(t, i)) continue;  // no point in this register
     const int p = F::out_pos(t, i);
     const int kx = kval(p, N);
     const uint32_t io0 = (uint32_t)((p * N + yi) * a.lo0.pitch + kz);

@@ -16,6 +16,11 @@ template <> struct FastOf<256> { using type = ns::Fast256; };
 template <> struct FastOf<324> { using type = ns::Fast324; };
 template <> struct FastOf<384> { using type = ns::Fast384; };
 template <> struct FastOf<512> { using type = ns::Fast512; };
+template <> struct FastOf<144> { using type = ns::Fast144; };
+template <> struct FastOf<160> { using type = ns::Fast160; };
+template <> struct FastOf<240> { using type = ns::Fast240; };
+template <> struct FastOf<270> { using type = ns::Fast270; };
+template <> struct FastOf<360> { using type = ns::Fast360; };
 
 // Specialised FP32 passes for one compile-time size (same semantics and layout).
 template <typename C, int OP, int FEED>

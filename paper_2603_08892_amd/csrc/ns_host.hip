@@ -103,8 +103,8 @@ const char* validate(const ns_config* c) {
 bool fast_size(const ns_config* c) {
   const int n = c->n;
   return c->precision == NS_FP32 && !(c->flags & NS_CFG_GENERIC_PASSES) &&
-         (n == 64 || n == 128 || n == 192 || n == 216 || n == 256 || n == 324 || n == 384 ||
-          n == 512);
+         (n == 64 || n == 128 || n == 144 || n == 160 || n == 192 || n == 216 || n == 240 || n == 256 ||
+          n == 270 || n == 324 || n == 360 || n == 384 || n == 512);
 }
 
 bool make_layout(const ns_config* c, Layout* lay) {
@@ -217,10 +217,15 @@ ns_status eval(ns_ctx* c, const Cx<R>* in, ns::Lay lin, const double* s, EpiArgs
     switch (c->fast) {
       case 64: return fast_eval<64, OP>(c, in, lin, sh, a, ch);
       case 128: return fast_eval<128, OP>(c, in, lin, sh, a, ch);
+      case 144: return fast_eval<144, OP>(c, in, lin, sh, a, ch);
+      case 160: return fast_eval<160, OP>(c, in, lin, sh, a, ch);
       case 192: return fast_eval<192, OP>(c, in, lin, sh, a, ch);
-      case 256: return fast_eval<256, OP>(c, in, lin, sh, a, ch);
       case 216: return fast_eval<216, OP>(c, in, lin, sh, a, ch);
+      case 240: return fast_eval<240, OP>(c, in, lin, sh, a, ch);
+      case 256: return fast_eval<256, OP>(c, in, lin, sh, a, ch);
+      case 270: return fast_eval<270, OP>(c, in, lin, sh, a, ch);
       case 324: return fast_eval<324, OP>(c, in, lin, sh, a, ch);
+      case 360: return fast_eval<360, OP>(c, in, lin, sh, a, ch);
       case 384: return fast_eval<384, OP>(c, in, lin, sh, a, ch);
       case 512: return fast_eval<512, OP>(c, in, lin, sh, a, ch);
       default: break;
@@ -565,10 +570,15 @@ ns_status adj_eval(ns_ctx* c, const Cx<R>* st, ns::Lay lst, const double* s, con
     switch (c->fast) {
       case 64: return fast_adj_eval<64, AOP>(c, st, lst, sh, la, aa);
       case 128: return fast_adj_eval<128, AOP>(c, st, lst, sh, la, aa);
+      case 144: return fast_adj_eval<144, AOP>(c, st, lst, sh, la, aa);
+      case 160: return fast_adj_eval<160, AOP>(c, st, lst, sh, la, aa);
       case 192: return fast_adj_eval<192, AOP>(c, st, lst, sh, la, aa);
-      case 256: return fast_adj_eval<256, AOP>(c, st, lst, sh, la, aa);
       case 216: return fast_adj_eval<216, AOP>(c, st, lst, sh, la, aa);
+      case 240: return fast_adj_eval<240, AOP>(c, st, lst, sh, la, aa);
+      case 256: return fast_adj_eval<256, AOP>(c, st, lst, sh, la, aa);
+      case 270: return fast_adj_eval<270, AOP>(c, st, lst, sh, la, aa);
       case 324: return fast_adj_eval<324, AOP>(c, st, lst, sh, la, aa);
+      case 360: return fast_adj_eval<360, AOP>(c, st, lst, sh, la, aa);
       case 384: return fast_adj_eval<384, AOP>(c, st, lst, sh, la, aa);
       case 512: return fast_adj_eval<512, AOP>(c, st, lst, sh, la, aa);
       default: break;

@@ -57,7 +57,7 @@ REFERENCE = "rk4_192_reference"
 # k_max = 108 (k^2 <= 11663), the resolution of Table S1: RK4 on 324^3 with 2/3
 # truncation as the reference; the grids of the table that are 2^a 3^b 5^c
 # (216 at C_t = 1, 240 at 0.9; 270 at 0.8 beside them) and 256 at C_t = 27/32.
-# 216, 256 and 324 run the specialised passes, 240 and 270 the size-generic ones.
+# Every grid here runs the specialised passes.
 KMAX108 = 107
 RUNS108 = {
     "rk4_324_reference": ("rk4", 324, 2.0 / 3.0, 1.0, "sphere"),

@@ -140,7 +140,8 @@ def test_vjp_specialised_passes_match_oracle(n, ct, mask, variant):
 
 
 @pytest.mark.parametrize("n,ct", [(128, 2 / 3), (192, 2 / 3), (256, 1.0), (216, 1.0), (324, 2 / 3),
-                                  (384, 512 / 3 / 192), (512, 2 / 3)])
+                                  (384, 512 / 3 / 192), (512, 2 / 3), (144, 1.0), (160, 0.8), (240, 0.9),
+                                  (270, 0.8), (360, 512 / 3 / 180)])
 def test_vjp_specialised_passes_match_generic(n, ct):
     """Specialised and size-generic adjoint passes agree to FP32 round-off."""
     from paper_2603_08892_amd import ns

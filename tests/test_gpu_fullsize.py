@@ -1,7 +1,8 @@
 """GPU parity against the FP64 oracle on dense fields at the full grid sizes of the
-measured workloads: the 384^3 grid of the forced-HIT pairing (PS-RK2 random at
-C_t = 8/9), the 512^3 grid of its RK4 side, and one-step and two-step parity of
-every scheme on the chained specialised passes at 128^3 and 192^3.
+measured workloads: the 384^3 and 360^3 grids of the forced-HIT pairing (PS-RK2
+random at C_t = 8/9 and 0.948), the 512^3 grid of its RK4 side, and one-step and
+two-step parity of the schemes on the chained specialised passes at 128^3 and 192^3
+and on the predicated plans at 144^3, 160^3, 240^3 and 270^3.
 
 At 384^3 and 512^3 the FP64 oracle takes one to three minutes per evaluation on
 the host, so those cases use dense inputs band-limited to |k| <= K0 (every mode
@@ -14,8 +15,8 @@ which the oracle evaluates exactly on a 256^3 grid holding the whole support
 (|k| <= 127) and is embedded into the full grid:
 * ns_nonlinear on 384^3 (all shifts, the two-shift average), K0 = 63: output
   support 126;
-* one forced PS-RK2 random step on 384^3, K0 = 31: the second stage's input has
-  support 62, its product 124;
+* one forced PS-RK2 random step on 384^3 and on 360^3, K0 = 31: the second stage's
+  input has support 62, its product 124;
 * one Lawson RK4 step on 512^3 at C_t = 2/3, K0 = 7: the stage supports double
   four times, up to 112.
 Shifts do not change an alias-free product, so the oracle runs unshifted.
@@ -100,18 +101,34 @@ def test_nonlinear_384_band_limited_all_shifts():
     _modes(_host(s.nonlinear(ud, ps_avg=True)), want, "384 ps_avg")
 
 
-def test_forced_ps_random_step_384_band_limited():
-    n, ct, k0, dt = 384, (512 / 3) / 192, 31, 1e-3
+_FORCED_STEP = {}
+
+
+def _forced_step_oracle(k0, dt, nu):
+    """The oracle's forced PS-RK2 random step of the band-limited field (the same for
+    every grid that holds its support, so computed once)."""
+    key = (k0, dt, nu)
+    if key not in _FORCED_STEP:
+        us = _band_limited(k0, 72, energy=1.5)
+        model = onl.NSModel(NS, nu, grid.mask(NS, 1.0))
+        o = oforcing.forcing(us, dt, 13, 5)
+        _FORCED_STEP[key] = (us, schemes.ps_heun(model, us, dt, oforcing.random_shift(9, 5), forcing=o))
+    return _FORCED_STEP[key]
+
+
+# the two coarse grids of the 512^3 comparison at the same k_max = 512/3: 384 (radix
+# 2 and 3) and 360 (radix 2, 3 and 5, some butterflies predicated off)
+@pytest.mark.parametrize("n", [384, 360])
+def test_forced_ps_random_step_band_limited(n):
+    ct, k0, dt = (512 / 3) / (n / 2), 31, 1e-3
     nu = (512 / 3) ** (-4 / 3)
     print(f"[fullsize] forced PS random step n={n} K0={k0}", flush=True)
-    us = _band_limited(k0, 72, energy=1.5)
-    model = onl.NSModel(NS, nu, grid.mask(NS, 1.0))
-    o = oforcing.forcing(us, dt, 13, 5)
-    want = _embed(schemes.ps_heun(model, us, dt, oforcing.random_shift(9, 5), forcing=o), NS, n)
+    us, step = _forced_step_oracle(k0, dt, nu)
+    want = _embed(step, NS, n)
     s = _solver(n, ct, nu, seed=9)
     ud = s.to_device(_embed(us, NS, n))
     s.step_ps(ud, dt, 1, "random", forcing={"seed": 13, "injection": 1.0}, step0=5)
-    _modes(_host(ud), want, "384 forced PS random step")
+    _modes(_host(ud), want, f"{n} forced PS random step")
 
 
 def test_rk4_step_512_band_limited():
@@ -139,7 +156,8 @@ def _dense(n, ct, seed, energy=0.5):
 # one step and two steps in one call (the second step's first x-inverse pass then
 # runs inside the first step's last x-forward pass) of every scheme, dense fields
 SCHEMES = [("random", 128, 1.0), ("approx", 128, 1.0), ("exact", 128, 1.0), ("rk4", 128, 2 / 3),
-           ("random", 192, 1.0), ("exact", 192, 1.0), ("rk4", 192, 2 / 3)]
+           ("random", 192, 1.0), ("exact", 192, 1.0), ("rk4", 192, 2 / 3),
+           ("random", 144, 128 / 144), ("exact", 160, 0.8), ("random", 240, 0.9), ("rk4", 270, 2 / 3)]
 
 
 @pytest.mark.parametrize("name,n,ct", SCHEMES)

@@ -328,12 +328,16 @@ def test_energy_conservation_on_gpu():
                                        (192, 2 / 3, "sphere"), (256, 1.0, "sphere"),
                                        (128, 1.0, "no_multiple_aliases"), (128, 2 / 3, "cube"),
                                        (192, 1.0, "rogallo"), (216, 1.0, "sphere"), (324, 2 / 3, "sphere"),
-                                       (384, 512 / 3 / 192, "sphere"), (512, 2 / 3, "sphere")])
+                                       (384, 512 / 3 / 192, "sphere"), (512, 2 / 3, "sphere"),
+                                       (144, 128 / 144, "sphere"), (160, 0.8, "sphere"), (160, 2 / 3, "cube"),
+                                       (240, 0.9, "sphere"), (240, 1.0, "no_multiple_aliases"),
+                                       (270, 0.8, "sphere"), (360, 512 / 3 / 180, "sphere")])
 def test_specialised_passes_match_generic(n, ct, mask):
-    """The compile-time FP32 passes (N = 64, 128, 192, 216, 256, 324, 384,
-    512) and the size-generic passes
-    agree to FP32 round-off (each is within ~5e-6 of the FP64 oracle), for the
-    nonlinear term and two steps of every scheme."""
+    """The compile-time FP32 passes (N = 64, 128, 144, 160, 192, 216, 240, 256, 270,
+    324, 360, 384, 512; at 160, 240, 270 and 360 some butterflies of a stage are
+    predicated off) and the size-generic passes agree to FP32 round-off (each is
+    within ~5e-6 of the FP64 oracle), for the nonlinear term and two steps of every
+    scheme."""
     print(f"[fast-vs-generic] n={n} ct={ct:.4f} mask={mask}", flush=True)
     nu, dt = 1 / 1600, 2e-3
     fast = _solver(n, ct, mask, nu=nu, seed=4)

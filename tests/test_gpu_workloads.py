@@ -1,7 +1,6 @@
 """The measured workloads at their full sizes, in the launch configurations the
-benchmark times (the specialised FP32 passes at N = 128, 192, 256 and 512; the
-generic passes at N = 360), against the FP64 oracle or against properties that
-hold at any size.
+benchmark times (the specialised FP32 passes at N = 128, 192, 256, 360, 384 and
+512), against the FP64 oracle or against properties that hold at any size.
 
 - Taylor-Green 128^3 (nu = 1/1600, dt = 2e-3): one step of each phase-shift
   variant on the 128^3 grid and of RK4 on the 192^3 grid with 2/3 truncation
@@ -172,8 +171,8 @@ def test_adjoint_128_fifty_steps():
 
 @pytest.mark.parametrize("n,ct", [(512, 2 / 3), (384, 512 / 3 / 192), (360, 0.9481)])
 def test_large_grids_taylor_green_closed_form(n, ct):
-    """512^3 and 384^3 on the specialised passes, 360^3 on the generic ones (no
-    specialised plan at that size); compared on the device."""
+    """512^3, 384^3 and 360^3 (whose plan predicates some butterflies off) on the
+    specialised passes; compared on the device."""
     import torch
     print(f"[workload] Taylor-Green closed form {n}^3 C_t={ct:.4f}", flush=True)
     s = _solver(n, ct, NU_TG)
@@ -198,8 +197,8 @@ def test_large_grids_taylor_green_closed_form(n, ct):
 
 @pytest.mark.parametrize("n,ct", [(360, 0.9481), (384, 512 / 3 / 192)])
 def test_large_grid_properties_and_energy_budget(n, ct):
-    """Seeded isotropic field on 360^3 (C_t = 0.9481, generic passes) and 384^3 (C_t = 8/9,
-    specialised passes), both at about the k_max of 512^3 at 2/3:
+    """Seeded isotropic field on 360^3 (C_t = 0.9481) and 384^3 (C_t = 8/9), both at
+    about the k_max of 512^3 at 2/3:
     <u, N> = 0, k.N = 0, N = 0 outside the mask, and one random-shift step changes the
     energy by the dissipation -2 nu sum w k^2 |u|^2 dt to O(dt^2)."""
     nu, dt = 2e-3, 2e-5
