@@ -598,8 +598,12 @@ using Fast256 = FastCfg<LP256b, LP256b, LP256b, 8, LP256b>;
 // line): the grids of the k_max = 108 comparison
 using LP216 = LinePlan<216, 18, Radices<12, 6, 3>, Radices<3, 6, 12>>;
 using LP324 = LinePlan<324, 27, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
-using Fast216 = FastCfg<LP216, LP216, LP216, 8, LP216>;
-using Fast324 = FastCfg<LP324, LP324, LP324, 8, LP324>;
+// z passes over 32 threads a line (two lines a wavefront, wavefront-scope
+// synchronisation instead of block barriers), some butterflies predicated off
+using LP216z = LinePlan<216, 32, Radices<6, 6, 6>, Radices<6, 6, 6>>;
+using LP324z = LinePlan<324, 32, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
+using Fast216 = FastCfg<LP216, LP216, LP216z, 4, LP216>;
+using Fast324 = FastCfg<LP324, LP324, LP324z, 4, LP324>;
 // 384 = 12 4 4 2 (inverse), 32 threads per line, four lines per z block
 using LP384 = LinePlan<384, 32, Radices<12, 4, 4, 2>, Radices<2, 4, 4, 12>>;
 using Fast384 = FastCfg<LP384, LP384, LP384, 4, LP384>;
@@ -626,10 +630,16 @@ using LP360 = LinePlan<360, 36, Radices<10, 6, 6>, Radices<6, 6, 10>>;
 // that a 16-column tile is a 480-thread block that may hold 256 registers a thread
 // (576 threads allow 168, and the x-forward passes spilled)
 using LP360x = LinePlan<360, 30, Radices<12, 6, 5>, Radices<5, 6, 12>>;
-using Fast144 = FastCfg<LP144, LP144, LP144, 8, LP144>;
+// z passes with lines inside one wavefront: 16 threads at 144, 32 at 240 and 270,
+// 64 at 360 (10 registers a transform)
+using LP144z = LinePlan<144, 16, Radices<12, 12>, Radices<12, 12>>;
+using LP240z = LinePlan<240, 32, Radices<10, 4, 6>, Radices<6, 4, 10>>;
+using LP270z = LinePlan<270, 32, Radices<9, 6, 5>, Radices<5, 6, 9>>;
+using LP360z = LinePlan<360, 64, Radices<10, 6, 6>, Radices<6, 6, 10>>;
+using Fast144 = FastCfg<LP144, LP144, LP144z, 8, LP144>;
 using Fast160 = FastCfg<LP160, LP160, LP160, 8, LP160>;
-using Fast240 = FastCfg<LP240, LP240, LP240, 8, LP240>;
-using Fast270 = FastCfg<LP270, LP270, LP270, 4, LP270>;  // 270^2 is not a multiple of 8
-using Fast360 = FastCfg<LP360x, LP360, LP360, 8, LP360x>;
+using Fast240 = FastCfg<LP240, LP240, LP240z, 4, LP240>;
+using Fast270 = FastCfg<LP270, LP270, LP270z, 4, LP270>;
+using Fast360 = FastCfg<LP360x, LP360, LP360z, 4, LP360x>;
 
 }  // namespace ns
