@@ -34,7 +34,6 @@ headline workload on the host cores.
 """
 
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -100,18 +99,10 @@ def pass_bytes(g):
     }
 
 
-def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2603_08892_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
-
-
-def committed_traffic(kernel, workload):
+def committed_traffic(kernel, workload, n):
     """HBM traffic per launch from the committed counter summary, if it was taken on
     the current kernel sources (else None)."""
+    from paper_2603_08892_amd.profsum import source_hash
     path = os.path.join(ROOT, "profiles", "traffic_counters.md")
     if not os.path.exists(path):
         return None
@@ -122,7 +113,7 @@ def committed_traffic(kernel, workload):
     rec = json.loads(m.group(1))
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("per_launch_bytes", {}).get(f"{workload}:{kernel}")
+    return rec.get("per_launch_bytes", {}).get(f"{workload}@{n}:{kernel}")
 
 
 def cfl_dt(u_hat, n, cfl):
@@ -201,7 +192,7 @@ def roofline(passes, n, k2max, workload):
     dom = max(per, key=lambda k: per[k]["avg_ms"] * per[k]["launches"])
     d = per[dom]
     return {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": committed_traffic(dom, workload),
+            "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": committed_traffic(dom, workload, n),
             "kernel": dom, "workload": workload, "bytes_per_launch": d["bytes"],
             "avg_launch_ms": round(d["avg_ms"], 5),
             "passes": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}

@@ -1,0 +1,154 @@
+"""Per-pass summaries of rocprofv3 output for the library's kernels.
+
+    python -m paper_2603_08892_amd.profsum trace DIR
+        kernel trace (rocprofv3 --kernel-trace --output-format csv -d DIR -o run):
+        launches and mean duration per grid size and pass
+    python -m paper_2603_08892_amd.profsum traffic FETCH_DIR WRITE_DIR WORKLOAD
+        two counter runs (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, of a
+        bench run with --copy-mb MiB): KiB per dispatch per pass, scaled by what the
+        same counters read for the calibration copy (torch.neg over MiB in and out),
+        and the JSON block that bench.py reads its roofline traffic from
+
+Passes are named as in bench.py: x_inverse, y_inverse, z_fused, y_forward,
+x_forward_epilogue (an x-forward pass on its own) and x_forward_inverse (an
+x-forward pass that also runs the next evaluation's x-inverse pass); the adjoint
+kernels as lam_x, z_adjoint, x_adjoint; everything else by kernel name.
+"""
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+
+
+def source_hash():
+    """Hash of every kernel source file (names and contents)."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def classify(name):
+    """(grid size or None, pass name) of a kernel name as rocprofv3 prints it."""
+    m = re.match(r"(?:void )?ns::(\w+)<ns::LinePlan<(\d+),", name)
+    if m:
+        kern, n = m.group(1), int(m.group(2))
+        if kern == "f_xinv":
+            return n, "x_inverse"
+        if kern == "f_ypass":
+            return n, "y_inverse" if re.search(r"> >, 1>\(", name) else "y_forward"
+        if kern == "f_zcross":
+            return n, "z_fused"
+        if kern == "f_xfwd":
+            feed = re.search(r"> >, -?\d+, (\d+)>\(", name)
+            return n, "x_forward_inverse" if feed and feed.group(1) != "0" else "x_forward_epilogue"
+        return n, {"f_xlam": "lam_x", "f_zadj": "z_adjoint", "f_xadj": "x_adjoint"}.get(kern, kern)
+    m = re.match(r"(?:void )?ns::(k_\w+)<", name) or re.match(r"(?:void )?ns::(k_\w+)\(", name)
+    if m:
+        kern = m.group(1)
+        generic = {"k_xinv": "x_inverse", "k_zcross": "z_fused", "k_xlam": "lam_x", "k_zadj": "z_adjoint",
+                   "k_xadj": "x_adjoint"}
+        if kern == "k_ypass":
+            return None, "y_inverse (generic)" if ", 1>(" in name else "y_forward (generic)"
+        if kern in generic:
+            return None, generic[kern] + " (generic)"
+        if kern == "k_xfwd":
+            return None, "x_forward (generic)"
+        return None, kern
+    return None, None
+
+
+def _rows(path, fname):
+    with open(os.path.join(path, fname)) as fh:
+        return list(csv.DictReader(fh))
+
+
+def trace(path):
+    """{(n, pass): [durations in us]} from a kernel-trace directory."""
+    out = collections.defaultdict(list)
+    for r in _rows(path, "run_kernel_trace.csv"):
+        n, p = classify(r["Kernel_Name"])
+        if p is None:
+            continue
+        out[(n, p)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    return out
+
+
+def counters(path, counter):
+    """({(n, pass): [KiB per dispatch]}, calibration KiB of the torch.neg copy or None)."""
+    out = collections.defaultdict(list)
+    calib = None
+    for r in _rows(path, "run_counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        name, v = r["Kernel_Name"], float(r["Counter_Value"])
+        if "neg_kernel" in name:
+            calib = v if calib is None else max(calib, v)
+            continue
+        n, p = classify(name)
+        if p is not None:
+            out[(n, p)].append(v)
+    return out, calib
+
+
+ORDER = ["x_inverse", "y_inverse", "z_fused", "y_forward", "x_forward_epilogue", "x_forward_inverse",
+         "lam_x", "z_adjoint", "x_adjoint"]
+
+
+def _key(k):
+    n, p = k
+    return (n or 0, ORDER.index(p) if p in ORDER else len(ORDER), p)
+
+
+def print_trace(path):
+    t = trace(path)
+    print("| N | pass | launches | mean us | total ms |")
+    print("|---|---|---|---|---|")
+    for k in sorted(t, key=_key):
+        d = t[k]
+        print(f"| {k[0] or '-'} | {k[1]} | {len(d)} | {sum(d) / len(d):.2f} | {sum(d) * 1e-3:.3f} |")
+
+
+def print_traffic(fetch_dir, write_dir, workload, copy_mib=256):
+    f, fc = counters(fetch_dir, "FETCH_SIZE")
+    w, wc = counters(write_dir, "WRITE_SIZE")
+    if fc is None or wc is None:
+        raise SystemExit("no calibration copy (torch.neg) in the counter runs: run the bench with --copy-mb")
+    ff, wf = copy_mib * 1024 / fc, copy_mib * 1024 / wc
+    print(f"calibration: torch.neg over {copy_mib} MiB reads FETCH_SIZE {fc:.0f} KiB, WRITE_SIZE {wc:.0f} KiB "
+          f"-> factors {ff:.4f} (fetch), {wf:.4f} (write)")
+    print("| N | pass | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB (scaled) | write MB | traffic MB |")
+    print("|---|---|---|---|---|---|---|---|")
+    per = {}
+    for k in sorted(set(f) & set(w), key=_key):
+        fk, wk = sum(f[k]) / len(f[k]), sum(w[k]) / len(w[k])
+        rd, wr = fk * 1024 * ff, wk * 1024 * wf
+        print(f"| {k[0] or '-'} | {k[1]} | {len(f[k])} | {fk:.0f} | {wk:.0f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+              f"{(rd + wr) / 1e6:.1f} |")
+        if k[0] is not None:
+            per[f"{workload}@{k[0]}:{k[1]}"] = int(round(rd + wr))
+    print("```json")
+    print(json.dumps({"source_hash": source_hash(), "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+                      "per_launch_bytes": per}, indent=1))
+    print("```")
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "trace":
+        print_trace(argv[1])
+    elif len(argv) >= 4 and argv[0] == "traffic":
+        print_traffic(argv[1], argv[2], argv[3], int(argv[4]) if len(argv) > 4 else 256)
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
