@@ -50,7 +50,6 @@ HBM_PEAK_GBS = 8000.0
 NU, DT = 1.0 / 1600.0, 2e-3
 NP, NR = 128, 192
 SPEC_EVERY = 10
-ELEM = 8  # bytes of one FP32 complex
 WORKLOADS = ("tg128", "hit256", "hit512", "adjoint", "tg32")
 
 
@@ -58,45 +57,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def geometry(n, k2max):
-    """Counts that fix the algorithmic bytes of the pruned passes (sphere k^2 <= k2max)."""
-    kmax = int(np.floor(np.sqrt(k2max)))
-    kzn = kmax + 1
-    i = np.arange(n)
-    k = np.where(i < n // 2, i, i - n)
-    kz = np.arange(kzn)
-    disk = (k[:, None] ** 2 + kz[None, :] ** 2) <= k2max          # (k_y, k_z) lines
-    A = int(disk.sum())
-    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + kz[None, None, :] ** 2
-    R = int((k2 <= k2max).sum())                                   # retained half-spectrum modes
-    return {"n": n, "kzn": kzn, "lines": A, "retained": R, "h": n // 2 + 1}
-
-
-def pass_bytes(g):
-    """Algorithmic HBM bytes per launch of each pass of the chained PS-RK2 random step.
-
-    x_inverse          reads the 3 retained components, writes 6 fields on the active lines
-                       (only the first evaluation of a call runs it on its own)
-    y_inverse          reads the 6 fields on the active lines, writes the full (x, y) planes k_z < kzn
-    z_fused            reads 6 and writes 3 fields on those planes
-    y_forward          reads 3 fields on the planes, writes them on the active lines
-    x_forward_epilogue the last stage of a call: reads 3 fields on the active lines and the
-                       partial update (retained modes), writes the state's whole half spectrum
-    x_forward_inverse  every other stage: reads 3 fields on the active lines and one stage
-                       operand, writes one stage output (retained modes; S1 only feeds the
-                       next evaluation and is not stored), then the next evaluation's 6
-                       fields on the active lines
-    """
-    n, A, R, kzn, h = g["n"], g["lines"], g["retained"], g["kzn"], g["h"]
-    planes = n * n * kzn
-    return {
-        "x_inverse": (3 * R + 6 * A * n) * ELEM,
-        "y_inverse": (6 * A * n + 6 * planes) * ELEM,
-        "z_fused": (6 * planes + 3 * planes) * ELEM,
-        "y_forward": (3 * planes + 3 * A * n) * ELEM,
-        "x_forward_epilogue": (3 * A * n + 3 * R + 3 * n * n * h) * ELEM,
-        "x_forward_inverse": (9 * A * n + 6 * R) * ELEM,
-    }
+from paper_2603_08892_amd.profsum import ELEM, geometry, pass_bytes  # noqa: E402  (the byte model)
 
 
 def committed_traffic(kernel, workload, n):

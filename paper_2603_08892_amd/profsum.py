@@ -1,8 +1,11 @@
 """Per-pass summaries of rocprofv3 output for the library's kernels.
 
-    python -m paper_2603_08892_amd.profsum trace DIR
+    python -m paper_2603_08892_amd.profsum trace DIR [--k2max K] [--rk4 N,...]
         kernel trace (rocprofv3 --kernel-trace --output-format csv -d DIR -o run):
-        launches and mean duration per grid size and pass
+        launches and mean duration per grid size and pass; with --k2max also the
+        algorithmic bytes of each pass (sphere k^2 <= K; the x-forward stage operands
+        of RK4 for the sizes after --rk4, of PS-RK2 for the others), GB/s and the
+        fraction of the 8 TB/s HBM peak
     python -m paper_2603_08892_amd.profsum traffic FETCH_DIR WRITE_DIR WORKLOAD
         two counter runs (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, of a
         bench run with --copy-mb MiB): KiB per dispatch per pass, scaled by what the
@@ -15,16 +18,67 @@ x-forward pass that also runs the next evaluation's x-inverse pass); the adjoint
 kernels as lam_x, z_adjoint, x_adjoint; everything else by kernel name.
 """
 
+import argparse
 import collections
 import csv
 import hashlib
 import json
 import os
 import re
-import sys
+
+import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
+
+
+ELEM = 8           # bytes of one FP32 complex
+HBM_PEAK_GBS = 8000.0
+
+
+def geometry(n, k2max):
+    """Counts that fix the algorithmic bytes of the pruned passes (sphere k^2 <= k2max)."""
+    kmax = int(np.floor(np.sqrt(k2max)))
+    kzn = kmax + 1
+    i = np.arange(n)
+    k = np.where(i < n // 2, i, i - n)
+    kz = np.arange(kzn)
+    disk = (k[:, None] ** 2 + kz[None, :] ** 2) <= k2max          # (k_y, k_z) lines
+    A = int(disk.sum())
+    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + kz[None, None, :] ** 2
+    R = int((k2 <= k2max).sum())                                   # retained half-spectrum modes
+    return {"n": n, "kzn": kzn, "lines": A, "retained": R, "h": n // 2 + 1}
+
+
+def pass_bytes(g, operands=6.0):
+    """Algorithmic HBM bytes per launch of each pass of a chained step (operands: stage
+    operands read and outputs stored per x-forward stage, in retained-mode fields:
+    6 for the PS-RK2 Heun stages (one operand read, one output stored, three
+    components each), 7.5 on average over the four Lawson RK4 stages, which read one,
+    two, two and one operand and store one output each).
+
+    x_inverse          reads the 3 retained components, writes 6 fields on the active lines
+                       (only the first evaluation of a call runs it on its own)
+    y_inverse          reads the 6 fields on the active lines, writes the full (x, y) planes k_z < kzn
+    z_fused            reads 6 and writes 3 fields on those planes
+    y_forward          reads 3 fields on the planes, writes them on the active lines
+    x_forward_epilogue the last stage of a call: reads 3 fields on the active lines and the
+                       partial update (retained modes), writes the state's whole half spectrum
+    x_forward_inverse  every other stage: reads 3 fields on the active lines and one stage
+                       operand, writes one stage output (retained modes; S1 only feeds the
+                       next evaluation and is not stored), then the next evaluation's 6
+                       fields on the active lines
+    """
+    n, A, R, kzn, h = g["n"], g["lines"], g["retained"], g["kzn"], g["h"]
+    planes = n * n * kzn
+    return {
+        "x_inverse": (3 * R + 6 * A * n) * ELEM,
+        "y_inverse": (6 * A * n + 6 * planes) * ELEM,
+        "z_fused": (6 * planes + 3 * planes) * ELEM,
+        "y_forward": (3 * planes + 3 * A * n) * ELEM,
+        "x_forward_epilogue": (3 * A * n + 3 * R + 3 * n * n * h) * ELEM,
+        "x_forward_inverse": int((9 * A * n + operands * R) * ELEM),
+    }
 
 
 def source_hash():
@@ -108,13 +162,27 @@ def _key(k):
     return (n or 0, ORDER.index(p) if p in ORDER else len(ORDER), p)
 
 
-def print_trace(path):
+def print_trace(path, k2max=None, rk4=()):
     t = trace(path)
-    print("| N | pass | launches | mean us | total ms |")
-    print("|---|---|---|---|---|")
+    if k2max is None:
+        print("| N | pass | launches | mean us | total ms |")
+        print("|---|---|---|---|---|")
+    else:
+        print("| N | pass | launches | mean us | total ms | algorithmic MB | GB/s | of 8 TB/s |")
+        print("|---|---|---|---|---|---|---|---|")
+    pb = {}
     for k in sorted(t, key=_key):
         d = t[k]
-        print(f"| {k[0] or '-'} | {k[1]} | {len(d)} | {sum(d) / len(d):.2f} | {sum(d) * 1e-3:.3f} |")
+        mean = sum(d) / len(d)
+        line = f"| {k[0] or '-'} | {k[1]} | {len(d)} | {mean:.2f} | {sum(d) * 1e-3:.3f} |"
+        if k2max is not None:
+            n = k[0]
+            if n is not None and n not in pb:
+                pb[n] = pass_bytes(geometry(n, k2max), 7.5 if n in rk4 else 6.0)
+            b = pb.get(n, {}).get(k[1])
+            line += (f" {b / 1e6:.1f} | {b / (mean * 1e-6) / 1e9:.0f} | {b / (mean * 1e-6) / 1e9 / HBM_PEAK_GBS:.3f} |"
+                     if b else " | | |")
+        print(line)
 
 
 def print_traffic(fetch_dir, write_dir, workload, copy_mib=256):
@@ -141,14 +209,24 @@ def print_traffic(fetch_dir, write_dir, workload, copy_mib=256):
     print("```")
 
 
-def main(argv):
-    if len(argv) >= 2 and argv[0] == "trace":
-        print_trace(argv[1])
-    elif len(argv) >= 4 and argv[0] == "traffic":
-        print_traffic(argv[1], argv[2], argv[3], int(argv[4]) if len(argv) > 4 else 256)
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("trace")
+    a.add_argument("dir")
+    a.add_argument("--k2max", type=int)
+    a.add_argument("--rk4", default="", help="comma list of grid sizes that ran RK4")
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("workload")
+    b.add_argument("--copy-mib", type=int, default=256)
+    args = ap.parse_args(argv)
+    if args.cmd == "trace":
+        print_trace(args.dir, args.k2max, tuple(int(x) for x in args.rk4.split(",") if x))
     else:
-        raise SystemExit(__doc__)
+        print_traffic(args.fetch_dir, args.write_dir, args.workload, args.copy_mib)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:])
+    main()
