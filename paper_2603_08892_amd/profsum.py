@@ -11,6 +11,12 @@
         bench run with --copy-mb MiB): KiB per dispatch per pass, scaled by what the
         same counters read for the calibration copy (torch.neg over MiB in and out),
         and the JSON block that bench.py reads its roofline traffic from
+    python -m paper_2603_08892_amd.profsum sq DIR
+        one counter run of the SQ counters SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS
+        SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU
+        SQ_LDS_BANK_CONFLICT: per pass, instructions per wave, the share of the
+        waves' lifetime spent issuing VALU instructions and the LDS bank-conflict
+        cycles per LDS instruction
 
 Passes are named as in bench.py: x_inverse, y_inverse, z_fused, y_forward,
 x_forward_epilogue (an x-forward pass on its own) and x_forward_inverse (an
@@ -185,6 +191,28 @@ def print_trace(path, k2max=None, rk4=()):
         print(line)
 
 
+SQ = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_WAVE_CYCLES",
+      "SQ_ACTIVE_INST_VALU", "SQ_LDS_BANK_CONFLICT")
+
+
+def print_sq(path):
+    vals = {c: counters(path, c)[0] for c in SQ}
+    print("| N | pass | dispatches | waves | VALU / wave | LDS / wave | VMEM rd / wr per wave | VALU-active share "
+          "of wave cycles | bank-conflict cycles / LDS instr |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for k in sorted(vals["SQ_WAVES"], key=_key):
+        if k[0] is None:
+            continue
+        m = {c: sum(vals[c][k]) / len(vals[c][k]) for c in SQ if vals[c].get(k)}
+        w = m.get("SQ_WAVES", 0.0)
+        if w <= 0 or len(m) < len(SQ):
+            continue
+        print(f"| {k[0]} | {k[1]} | {len(vals['SQ_WAVES'][k])} | {w:.0f} | {m['SQ_INSTS_VALU'] / w:.0f} | "
+              f"{m['SQ_INSTS_LDS'] / w:.0f} | {m['SQ_INSTS_VMEM_RD'] / w:.0f} / {m['SQ_INSTS_VMEM_WR'] / w:.0f} | "
+              f"{m['SQ_ACTIVE_INST_VALU'] / m['SQ_WAVE_CYCLES']:.2f} | "
+              f"{m['SQ_LDS_BANK_CONFLICT'] / max(m['SQ_INSTS_LDS'], 1.0):.2f} |")
+
+
 def print_traffic(fetch_dir, write_dir, workload, copy_mib=256):
     f, fc = counters(fetch_dir, "FETCH_SIZE")
     w, wc = counters(write_dir, "WRITE_SIZE")
@@ -221,9 +249,13 @@ def main(argv=None):
     b.add_argument("write_dir")
     b.add_argument("workload")
     b.add_argument("--copy-mib", type=int, default=256)
+    c = sub.add_parser("sq")
+    c.add_argument("dir")
     args = ap.parse_args(argv)
     if args.cmd == "trace":
         print_trace(args.dir, args.k2max, tuple(int(x) for x in args.rk4.split(",") if x))
+    elif args.cmd == "sq":
+        print_sq(args.dir)
     else:
         print_traffic(args.fetch_dir, args.write_dir, args.workload, args.copy_mib)
 
