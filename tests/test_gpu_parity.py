@@ -331,7 +331,10 @@ def test_energy_conservation_on_gpu():
                                        (384, 512 / 3 / 192, "sphere"), (512, 2 / 3, "sphere"),
                                        (144, 128 / 144, "sphere"), (160, 0.8, "sphere"), (160, 2 / 3, "cube"),
                                        (240, 0.9, "sphere"), (240, 1.0, "no_multiple_aliases"),
-                                       (270, 0.8, "sphere"), (360, 512 / 3 / 180, "sphere")])
+                                       (270, 0.8, "sphere"), (360, 512 / 3 / 180, "sphere"),
+                                       # few retained modes: one k_z tile, most rows pruned
+                                       (160, 0.1, "sphere"), (270, 0.05, "sphere"), (360, 0.02, "cube"),
+                                       (144, 1.0, "rogallo")])
 def test_specialised_passes_match_generic(n, ct, mask):
     """The compile-time FP32 passes (N = 64, 128, 144, 160, 192, 216, 240, 256, 270,
     324, 360, 384, 512; at 160, 240, 270 and 360 some butterflies of a stage are
