@@ -88,16 +88,20 @@ struct LinePlan {
   using Fwd = Fwd_;   // radices of the forward transforms (reverse order of Inv)
 };
 
-// Plans of the five passes of one size; PZ = lines per block of the z pass.
-template <typename XI, typename YP, typename ZP, int PZ_, typename XF>
+// Plans of the five passes of one size; PZ = lines per block of the z pass; the
+// adjoint z pass (five inverse and three forward slices) may take its own plan ZA
+// with PZA lines per block.
+template <typename XI, typename YP, typename ZP, int PZ_, typename XF, typename ZA = ZP, int PZA_ = PZ_>
 struct FastCfg {
   static constexpr int N = XI::N;
   static_assert(8ull * N * N * (N / 2 + 1) < (1ull << 32), "32-bit byte offsets need 8 N^2 (N/2+1) < 2^32");
   static constexpr int PZ = PZ_;
-  static_assert(N * N % PZ_ == 0, "the z pass runs N^2 / PZ blocks of PZ whole lines");
+  static constexpr int PZA = PZA_;
+  static_assert(N * N % PZ_ == 0 && N * N % PZA_ == 0, "the z passes run N^2 / P blocks of P whole lines");
   using XInv = XI;
   using Y = YP;
   using Z = ZP;
+  using ZAdj = ZA;
   using XFwd = XF;
 };
 
@@ -592,21 +596,30 @@ using LP192 = LinePlan<192, 16, Radices<12, 4, 4>, Radices<4, 4, 12>>;
 using LP256b = LinePlan<256, 32, Radices<8, 8, 4>, Radices<4, 8, 8>>;
 using Fast64 = FastCfg<LP64, LP64, LP64, 16, LP64>;
 using Fast128 = FastCfg<LP128b, LP128b, LP128b, 8, LP128b>;
-using Fast192 = FastCfg<LP192, LP192, LP192, 8, LP192>;
+// z pass of 192: 6 8 4 over 32 threads, 8 registers a transform (the adjoint z
+// pass keeps 12 4 4 over 16)
+using LP192z = LinePlan<192, 32, Radices<6, 8, 4>, Radices<4, 8, 6>>;
+using Fast192 = FastCfg<LP192, LP192, LP192z, 8, LP192, LP192, 8>;
 using Fast256 = FastCfg<LP256b, LP256b, LP256b, 8, LP256b>;
 // 216 = 12 6 3 and 324 = 12 3 3 3 with 12 points per thread (18 and 27 threads per
 // line): the grids of the k_max = 108 comparison
 using LP216 = LinePlan<216, 18, Radices<12, 6, 3>, Radices<3, 6, 12>>;
 using LP324 = LinePlan<324, 27, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
-// z passes over 32 threads a line (two lines a wavefront, wavefront-scope
-// synchronisation instead of block barriers), some butterflies predicated off
-using LP216z = LinePlan<216, 32, Radices<6, 6, 6>, Radices<6, 6, 6>>;
-using LP324z = LinePlan<324, 32, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
+// z passes with the line inside one wavefront (wavefront-scope synchronisation
+// instead of block barriers) and few registers a thread (more waves per SIMD),
+// some butterflies predicated off: 216 = 8 3 9 over 32 threads (9 registers),
+// 324 = 6 6 9 over 64 (9); the adjoint z pass of 324 keeps 12 3 3 3 over 32
+using LP216z = LinePlan<216, 32, Radices<8, 3, 9>, Radices<9, 3, 8>>;
+using LP324z = LinePlan<324, 64, Radices<6, 6, 9>, Radices<9, 6, 6>>;
+using LP324za = LinePlan<324, 32, Radices<12, 3, 3, 3>, Radices<3, 3, 3, 12>>;
 using Fast216 = FastCfg<LP216, LP216, LP216z, 4, LP216>;
-using Fast324 = FastCfg<LP324, LP324, LP324z, 4, LP324>;
+using Fast324 = FastCfg<LP324, LP324, LP324z, 4, LP324, LP324za, 4>;
 // 384 = 12 4 4 2 (inverse), 32 threads per line, four lines per z block
 using LP384 = LinePlan<384, 32, Radices<12, 4, 4, 2>, Radices<2, 4, 4, 12>>;
-using Fast384 = FastCfg<LP384, LP384, LP384, 4, LP384>;
+// z pass of 384: 6 8 8 over 64 threads, 8 registers and two exchanges a transform
+// (the adjoint z pass keeps 12 4 4 2 over 32)
+using LP384z = LinePlan<384, 64, Radices<6, 8, 8>, Radices<8, 8, 6>>;
+using Fast384 = FastCfg<LP384, LP384, LP384z, 4, LP384, LP384, 4>;
 // 512 (the 2/3-truncated RK4 grid of the 512^3 comparison): y and z passes 8 8 8
 // with one wavefront per line, four lines per z block (at eight, one 512-thread
 // block of about 130 registers a thread is all a CU holds); x passes 16 8 4 with
@@ -619,8 +632,8 @@ using Fast512 = FastCfg<LP512x, LP512, LP512, 4, LP512x>;
 // Grids whose radices do not all divide one points-per-thread count: 12 registers
 // a thread, some butterflies of a stage predicated off (fft_reg.hpp).  144 = 12 12
 // (uniform, 12 threads), 160 = 10 4 4 (16), 240 = 10 4 6 (24), 270 = 9 6 5 (30),
-// 360 = 10 6 6 (36, the y and z passes): the truncation sweeps at k_max = 64 and 108 and the coarse
-// grid of the 512^3 comparison at C_t = 0.948.
+// 360 = 10 6 6 (36, the y pass): the truncation sweeps at k_max = 64 and 108 and the
+// coarse grid of the 512^3 comparison at C_t = 0.948.
 using LP144 = LinePlan<144, 12, Radices<12, 12>, Radices<12, 12>>;
 using LP160 = LinePlan<160, 16, Radices<10, 4, 4>, Radices<4, 4, 10>>;
 using LP240 = LinePlan<240, 24, Radices<10, 4, 6>, Radices<6, 4, 10>>;
@@ -630,16 +643,20 @@ using LP360 = LinePlan<360, 36, Radices<10, 6, 6>, Radices<6, 6, 10>>;
 // that a 16-column tile is a 480-thread block that may hold 256 registers a thread
 // (576 threads allow 168, and the x-forward passes spilled)
 using LP360x = LinePlan<360, 30, Radices<12, 6, 5>, Radices<5, 6, 12>>;
-// z passes with lines inside one wavefront: 16 threads at 144, 32 at 240 and 270,
-// 64 at 360 (10 registers a transform)
-using LP144z = LinePlan<144, 16, Radices<12, 12>, Radices<12, 12>>;
-using LP240z = LinePlan<240, 32, Radices<10, 4, 6>, Radices<6, 4, 10>>;
-using LP270z = LinePlan<270, 32, Radices<9, 6, 5>, Radices<5, 6, 9>>;
-using LP360z = LinePlan<360, 64, Radices<10, 6, 6>, Radices<6, 6, 10>>;
+// z passes with lines inside one wavefront and few registers a thread: 144 = 6 6 4,
+// 160 = 4 8 5, 240 = 8 6 5, 270 = 10 3 9, 360 = 12 6 5, all over 32 threads (8 to
+// 15 registers a transform); the adjoint z passes of 160 and 360, which hold eight
+// slices, keep 10 4 4 over 16 and 10 6 6 over 64
+using LP144z = LinePlan<144, 32, Radices<6, 6, 4>, Radices<4, 6, 6>>;
+using LP240z = LinePlan<240, 32, Radices<8, 6, 5>, Radices<5, 6, 8>>;
+using LP270z = LinePlan<270, 32, Radices<10, 3, 9>, Radices<9, 3, 10>>;
+using LP360z = LinePlan<360, 32, Radices<12, 6, 5>, Radices<5, 6, 12>>;
+using LP360za = LinePlan<360, 64, Radices<10, 6, 6>, Radices<6, 6, 10>>;
 using Fast144 = FastCfg<LP144, LP144, LP144z, 8, LP144>;
-using Fast160 = FastCfg<LP160, LP160, LP160, 8, LP160>;
+using LP160z = LinePlan<160, 32, Radices<4, 8, 5>, Radices<5, 8, 4>>;
+using Fast160 = FastCfg<LP160, LP160, LP160z, 8, LP160, LP160, 8>;
 using Fast240 = FastCfg<LP240, LP240, LP240z, 4, LP240>;
 using Fast270 = FastCfg<LP270, LP270, LP270z, 4, LP270>;
-using Fast360 = FastCfg<LP360x, LP360, LP360z, 4, LP360x>;
+using Fast360 = FastCfg<LP360x, LP360, LP360z, 4, LP360x, LP360za, 4>;
 
 }  // namespace ns

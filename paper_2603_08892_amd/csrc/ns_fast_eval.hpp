@@ -89,7 +89,7 @@ ns_status adj_eval_fast(ns_ctx* c, const Cx<float>* st, ns::Lay lst, const ns::S
   const Layout& l = c->lay;
   const Geom& g = l.g;
   Ptrs<float> p = ptrs<float>(c);
-  constexpr int N = C::N, P = C::PZ;
+  constexpr int N = C::N, P = C::PZA;
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
     hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
@@ -98,7 +98,7 @@ ns_status adj_eval_fast(ns_ctx* c, const Cx<float>* st, ns::Lay lst, const ns::S
                        c->stream, la, p.W, p.tw, sh, p.tiles, g);
     hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(9 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
                        c->stream, p.W, p.tw, l.ntz, g);
-    hipLaunchKernelGGL((ns::f_zadj<typename C::Z, P>), dim3(N * N / P), dim3(P * C::Z::TPL), 0, c->stream,
+    hipLaunchKernelGGL((ns::f_zadj<typename C::ZAdj, P>), dim3(N * N / P), dim3(P * C::ZAdj::TPL), 0, c->stream,
                        p.W, p.tw, g);
     hipLaunchKernelGGL((ns::f_ypass<typename C::Y, -1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
                        c->stream, p.W, p.tw, l.ntz, g);
