@@ -10,8 +10,8 @@
 // owned by t.  LDS: the exchange buffer [position][column] (row pitch L + 1 to
 // spread banks) and the twiddle table.
 // Contiguous pass (z): a block holds P lines, thread (p, t) = (tid div TPL, tid mod TPL);
-// a line's threads synchronise at wavefront scope when TPL divides 64 and with
-// block barriers otherwise (N = 144, 216, 240, 270, 324, 360).
+// a line's threads synchronise at wavefront scope when TPL divides 64 (every z plan
+// below) and with block barriers otherwise.
 // In the step sequences the x-forward kernel can also run the next evaluation's
 // x-inverse pass on its tile (template argument FEED), so a chained evaluation is
 // four launches: y-inverse, z, y-forward, x-forward (+ next x-inverse).
