@@ -45,6 +45,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2603_08892_amd.profsum import geometry, pass_bytes, source_hash  # noqa: E402  (the byte model)
+
 METRIC = "Mgridpts·RKsteps/s at matched kmax (PS-RK2 vs 2/3-RK4); HBM GB/s % of peak"
 HBM_PEAK_GBS = 8000.0
 NU, DT = 1.0 / 1600.0, 2e-3
@@ -57,13 +59,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-from paper_2603_08892_amd.profsum import ELEM, geometry, pass_bytes  # noqa: E402  (the byte model)
-
 
 def committed_traffic(kernel, workload, n):
     """HBM traffic per launch from the committed counter summary, if it was taken on
     the current kernel sources (else None)."""
-    from paper_2603_08892_amd.profsum import source_hash
     path = os.path.join(ROOT, "profiles", "traffic_counters.md")
     if not os.path.exists(path):
         return None
