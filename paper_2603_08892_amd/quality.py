@@ -4,7 +4,7 @@ index of Sec. "Performance and accuracy for a decaying flow" (Eq. quality; its
 discrete form in the appendix, with the wavenumber sum starting at k = 1)
 against a dealiased reference run.
 
-    python -m paper_2603_08892_amd.quality [--t-start 7 --t-end 12 --every 0.1] [--sweep]
+    python -m paper_2603_08892_amd.quality [--t-start 7 --t-end 12 --every 0.1] [--sweep] [--kmax 108]
 
 prints one JSON object: per run the grid, truncation, error index (percent),
 wall time and speedup over the reference (at equal dt, and under the paper's
