@@ -1,7 +1,9 @@
 // ns_fast.hpp -- compile-time specialised passes for the common grid sizes (FP32, gfx950).
 //
 // Same scratch layout, tile list and pass semantics as the generic kernels of
-// ns_kernels.hpp; the transforms run on registers (fft_reg.hpp) with one LDS
+// ns_kernels.hpp, except that in the step sequences the x-inverse passes store
+// the five transforms they compute and the y-inverse pass (f_ycurl) forms the
+// vorticity from them; the transforms run on registers (fft_reg.hpp) with one LDS
 // exchange per radix boundary instead of one LDS round trip per stage, and all
 // indices are compile-time except the thread and block coordinates.
 //
@@ -90,10 +92,14 @@ struct LinePlan {
 
 // Plans of the five passes of one size; PZ = lines per block of the z pass; the
 // adjoint z pass (five inverse and three forward slices) may take its own plan ZA
-// with PZA lines per block.
-template <typename XI, typename YP, typename ZP, int PZ_, typename XF, typename ZA = ZP, int PZA_ = PZ_>
+// with PZA lines per block.  YC: the step sequences run f_xinv<XI, false> and
+// f_ycurl (the vorticity formed in the y-inverse pass, five scratch fields written
+// by the x-inverse passes) instead of f_xinv<XI, true> and f_ypass over six fields.
+template <typename XI, typename YP, typename ZP, int PZ_, typename XF, typename ZA = ZP, int PZA_ = PZ_,
+          bool YC_ = false>
 struct FastCfg {
   static constexpr int N = XI::N;
+  static constexpr bool YC = YC_;
   static_assert(8ull * N * N * (N / 2 + 1) < (1ull << 32), "32-bit byte offsets need 8 N^2 (N/2+1) < 2^32");
   static constexpr int PZ = PZ_;
   static constexpr int PZA = PZA_;
@@ -112,7 +118,13 @@ struct FastCfg {
 // omega_z = i k_x u_y - i k_y u_x need only D_z = X(i k_x u_z) and D_y = X(i k_x u_y)
 // beside the velocity transforms: five transforms for six fields, and each state
 // component is read once per tile.
-template <typename C>
+// CURL = true stores the vorticity itself (fields 0..5 = u_x, u_y, u_z, omega_x,
+// omega_y, omega_z), as f_ypass reads it (the transposed evaluations and the sizes
+// without FastCfg::YC).  CURL = false stores the five transforms as they are: u_x,
+// u_y, u_z in fields 0, 1, 2, D_z in field 4 and D_y in field 5, and leaves field
+// 3 alone; f_ycurl forms the vorticity from them as it loads them, so a tile
+// writes five fields here and is read as five there instead of six.
+template <typename C, bool CURL>
 __global__ void __launch_bounds__(kFastL * C::TPL)
 f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg,
         Shift sh, const int2* __restrict__ tiles, Geom g) {
@@ -138,7 +150,7 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   }
   const LineView<float, kFastLp> lv{xb + l};
   const uint32_t sbase = (uint32_t)(yi * ls.pitch + kz0) + l, sstep = (uint32_t)(N * ls.pitch);
-  const float kyf = float(ky), kzf = float(kz);
+  [[maybe_unused]] const float kyf = float(ky), kzf = float(kz);
   Cx<float> ux[EPT], uy[EPT], uz[EPT], dy[EPT], dz[EPT];
   {
     bool ok[EPT];
@@ -182,18 +194,24 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
   store(1, uy);
   F::run(uz, t, lv, tw);
   store(2, uz);
+  if constexpr (CURL) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) uy[i] = mul_i(scale(uz[i], kyf) - scale(uy[i], kzf));  // omega_x
-  store(3, uy);
+    for (int i = 0; i < EPT; ++i) uy[i] = mul_i(scale(uz[i], kyf) - scale(uy[i], kzf));  // omega_x
+    store(3, uy);
+  }
   F::run(ux, t, lv, tw);
   store(0, ux);
   F::run(dz, t, lv, tw);
+  if constexpr (CURL) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) dz[i] = mul_i(scale(ux[i], kzf)) - dz[i];  // omega_y
+    for (int i = 0; i < EPT; ++i) dz[i] = mul_i(scale(ux[i], kzf)) - dz[i];  // omega_y
+  }
   store(4, dz);
   F::run(dy, t, lv, tw);
+  if constexpr (CURL) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) dy[i] = dy[i] - mul_i(scale(ux[i], kyf));  // omega_z
+    for (int i = 0; i < EPT; ++i) dy[i] = dy[i] - mul_i(scale(ux[i], kyf));  // omega_z
+  }
   store(5, dy);
 }
 
@@ -231,6 +249,91 @@ f_ypass(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, G
       if (F::out_ok(t, i) && (S > 0 || abs(kval(p, N)) <= yb)) st_off(base, (uint32_t)(p * g.kzp) + rbase, v[i]);
     }
   }
+}
+
+// ------------------------------------------------------------------ y inverse with the curl
+// The y-inverse pass of the step sequences of the sizes with FastCfg::YC, after
+// f_xinv<C, false> (or the fused x-forward pass), which stores u_x, u_y, u_z, D_z
+// and D_y in scratch fields 0, 1, 2, 4, 5.  A point here has fixed k_y and k_z,
+// so the vorticity is a pointwise combination of the stored transforms,
+//   omega_x = i (k_y u_z - k_z u_y),  omega_y = i k_z u_x - D_z,  omega_z = D_y - i k_y u_x,
+// formed in registers before the y transform.  Block group 0 reads u_y, u_z and
+// writes u_y, u_z, omega_x (fields 1, 2, 3); group 1 reads u_x, D_z, D_y and writes
+// u_x, omega_y, omega_z (fields 0, 4, 5).  Each field is read once; a block's
+// loads all come before its stores and no other block touches its fields on its
+// (x, k_z tile), so the pass runs in place.  Output as f_ypass<C, +1> over six
+// fields.  Three line buffers a thread: at 12 points a thread or over more than
+// 32 threads a line this allows one block per CU, where the six single-field
+// blocks of f_ypass keep two or three resident and are faster.
+template <typename C>
+__global__ void __launch_bounds__(kFastL * C::TPL)
+f_ycurl(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, Geom g) {
+  constexpr int N = C::N, TPL = C::TPL, EPT = C::EPT;
+  using F = RegFft<N, TPL, +1, typename C::Inv>;
+  __shared__ Cx<float> tw[N];
+  __shared__ Cx<float> xb[N * kFastLp];
+  const int tid = threadIdx.x;
+  const int l = tid % kFastL, t = tid / kFastL;
+  const int b = blockIdx.x;
+  const int kzt = b % ntz, rest = b / ntz;
+  const int x = rest % N, grp = rest / N;
+  const int kz0 = kzt * kFastL, kz = kz0 + l;
+  const int yb = ybound(g, kz0);
+  for (int i = tid; i < N; i += kFastL * TPL) tw[i] = twg[i];
+  const bool col = kz < g.kzn;
+  Cx<float>* const Wa = W + (grp ? 0 : 1) * g.wcomp;
+  Cx<float>* const Wb = W + (grp ? 4 : 2) * g.wcomp;
+  Cx<float>* const Wc = W + (grp ? 5 : 3) * g.wcomp;
+  const uint32_t rbase = (uint32_t)(x * N * g.kzp + kz0) + l;
+  const LineView<float, kFastLp> lv{xb + l};
+  Cx<float> va[EPT], vb[EPT], vc[EPT];
+  {
+    bool ok[EPT];
+    uint32_t idx[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = F::in_at(t, i);
+      ok[i] = col && F::in_ok(t, i) && abs(kval(p, N)) <= yb;
+      idx[i] = (uint32_t)(p * g.kzp) + rbase;
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      va[i] = ld_masked(Wa, idx[i], ok[i]);
+      vb[i] = ld_masked(Wb, idx[i], ok[i]);
+    }
+    if (grp) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) vc[i] = ld_masked(Wc, idx[i], ok[i]);
+    }
+  }
+  const float kzf = float(kz);
+  if (grp) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const float kyf = float(kval(F::in_at(t, i), N));
+      vb[i] = mul_i(scale(va[i], kzf)) - vb[i];  // omega_y
+      vc[i] = vc[i] - mul_i(scale(va[i], kyf));  // omega_z
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const float kyf = float(kval(F::in_at(t, i), N));
+      vc[i] = mul_i(scale(vb[i], kyf) - scale(va[i], kzf));  // omega_x
+    }
+  }
+  auto store = [&](Cx<float>* base, const Cx<float>* v) {
+    if (col) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        if (F::out_ok(t, i)) st_off(base, (uint32_t)(F::out_pos(t, i) * g.kzp) + rbase, v[i]);
+    }
+  };
+  F::run(va, t, lv, tw);
+  store(Wa, va);
+  F::run(vb, t, lv, tw);
+  store(Wb, vb);
+  F::run(vc, t, lv, tw);
+  store(Wc, vc);
 }
 
 // ------------------------------------------------------------------ z fused
@@ -334,8 +437,8 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
 // the input positions of the inverse transform (its first radix is the forward
 // transform's last), so the tile is not read back.  An out1 that only feeds the
 // next evaluation is not stored.  FEED needs a.full == 0 (the blocks are then the
-// active tiles, the same as the x-inverse pass).
-template <typename C, int OP, int FEED>
+// active tiles, the same as the x-inverse pass); CURL as in f_xinv.
+template <typename C, int OP, int FEED, bool CURL>
 __global__ void __launch_bounds__(kFastL * C::TPL)
 f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, Shift sh2,
        const int2* __restrict__ tiles, Geom g, EpiArgs<float> a) {
@@ -540,9 +643,10 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
   }
   }
   if constexpr (FEED != 0) {
-    // the next evaluation's x-inverse pass on this tile (as f_xinv, from registers)
+    // the next evaluation's x-inverse pass on this tile (as f_xinv<C, CURL>, from registers)
     const bool col = kz < g.kzn;
     Cx<float> ux[EPT], uy[EPT], uz[EPT], dy[EPT], dz[EPT];
+    [[maybe_unused]] const float kyf = float(ky), kzf = float(kz);
     const Cx<float> phyz2 = sh2.on ? phc2[l] : cx(1.f, 0.f);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -560,7 +664,6 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
       dy[i] = mul_i(scale(uy[i], kxf));
       dz[i] = mul_i(scale(uz[i], kxf));
     }
-    const float kyf = float(ky), kzf = float(kz);
     const uint32_t obase = (uint32_t)(yi * g.kzp + kz0) + l, ostep = (uint32_t)(N * g.kzp);
     auto store = [&](int f, const Cx<float>* v) {
       if (col) {
@@ -573,29 +676,41 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
     store(1, uy);
     FI::run(uz, t, lv, tw);
     store(2, uz);
+    if constexpr (CURL) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) uy[i] = mul_i(scale(uz[i], kyf) - scale(uy[i], kzf));  // omega_x
-    store(3, uy);
+      for (int i = 0; i < EPT; ++i) uy[i] = mul_i(scale(uz[i], kyf) - scale(uy[i], kzf));  // omega_x
+      store(3, uy);
+    }
     FI::run(ux, t, lv, tw);
     store(0, ux);
     FI::run(dz, t, lv, tw);
+    if constexpr (CURL) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) dz[i] = mul_i(scale(ux[i], kzf)) - dz[i];  // omega_y
+      for (int i = 0; i < EPT; ++i) dz[i] = mul_i(scale(ux[i], kzf)) - dz[i];  // omega_y
+    }
     store(4, dz);
     FI::run(dy, t, lv, tw);
+    if constexpr (CURL) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) dy[i] = dy[i] - mul_i(scale(ux[i], kyf));  // omega_z
+      for (int i = 0; i < EPT; ++i) dy[i] = dy[i] - mul_i(scale(ux[i], kyf));  // omega_z
+    }
     store(5, dy);
   }
 }
 
 // Specialised sizes (FP32).  The forward radix list is the inverse one reversed.
+// YC (the vorticity formed in the y-inverse pass, f_ycurl) is on for 128, 144, 256
+// and 270, where the x-inverse passes writing five fields instead of six gain more
+// than the y-inverse pass loses to its three-field blocks: PS-RK2 random steps
+// 3.3%, 1.3%, 2.8% and 1.5% faster.  At 64, 160, 192, 216, 324, 360, 384 and 512
+// those blocks leave one or two resident a CU and the step was 0.3% to 13% slower;
+// 240 was unchanged.
 using LP64 = LinePlan<64, 8, Radices<8, 8>, Radices<8, 8>>;
 using LP128b = LinePlan<128, 16, Radices<8, 4, 4>, Radices<4, 4, 8>>;
 using LP192 = LinePlan<192, 16, Radices<12, 4, 4>, Radices<4, 4, 12>>;
 using LP256b = LinePlan<256, 32, Radices<8, 8, 4>, Radices<4, 8, 8>>;
 using Fast64 = FastCfg<LP64, LP64, LP64, 16, LP64>;
-using Fast128 = FastCfg<LP128b, LP128b, LP128b, 8, LP128b>;
+using Fast128 = FastCfg<LP128b, LP128b, LP128b, 8, LP128b, LP128b, 8, true>;
 // z pass of 192: 6 8 4 over 32 threads, 8 registers a transform (the adjoint z
 // pass keeps 12 4 4 over 16)
 using LP192z = LinePlan<192, 32, Radices<6, 8, 4>, Radices<4, 8, 6>>;
@@ -604,7 +719,7 @@ using Fast192 = FastCfg<LP192, LP192, LP192z, 8, LP192, LP192, 8>;
 // SIMD; 5% faster than 8 8 4 over 32 at 256^3, whose extra exchange costs more at
 // 128^3); the adjoint z pass keeps 8 8 4 over 32
 using LP256z = LinePlan<256, 64, Radices<4, 4, 4, 4>, Radices<4, 4, 4, 4>>;
-using Fast256 = FastCfg<LP256b, LP256b, LP256z, 4, LP256b, LP256b, 8>;
+using Fast256 = FastCfg<LP256b, LP256b, LP256z, 4, LP256b, LP256b, 8, true>;
 // 216 = 12 6 3 and 324 = 12 3 3 3 with 12 points per thread (18 and 27 threads per
 // line): the grids of the k_max = 108 comparison
 using LP216 = LinePlan<216, 18, Radices<12, 6, 3>, Radices<3, 6, 12>>;
@@ -660,11 +775,11 @@ using LP240z = LinePlan<240, 32, Radices<8, 6, 5>, Radices<5, 6, 8>>;
 using LP270z = LinePlan<270, 32, Radices<10, 3, 9>, Radices<9, 3, 10>>;
 using LP360z = LinePlan<360, 32, Radices<12, 6, 5>, Radices<5, 6, 12>>;
 using LP360za = LinePlan<360, 64, Radices<10, 6, 6>, Radices<6, 6, 10>>;
-using Fast144 = FastCfg<LP144, LP144, LP144z, 8, LP144>;
+using Fast144 = FastCfg<LP144, LP144, LP144z, 8, LP144, LP144z, 8, true>;
 using LP160z = LinePlan<160, 32, Radices<4, 8, 5>, Radices<5, 8, 4>>;
 using Fast160 = FastCfg<LP160, LP160, LP160z, 8, LP160, LP160, 8>;
 using Fast240 = FastCfg<LP240z, LP240, LP240z, 4, LP240z>;
-using Fast270 = FastCfg<LP270, LP270, LP270z, 4, LP270>;
+using Fast270 = FastCfg<LP270, LP270, LP270z, 4, LP270, LP270z, 4, true>;
 using Fast360 = FastCfg<LP360x, LP360, LP360z, 4, LP360x, LP360za, 4>;
 
 }  // namespace ns

@@ -35,13 +35,17 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift
   if (ntiles > 0) {
     if (front) {
       if ((e = tstart(c, 0)) != hipSuccess) return hip_check(c, e, "timing event");
-      hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
+      hipLaunchKernelGGL((ns::f_xinv<typename C::XInv, !C::YC>), dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
                          c->stream, in, lin, p.W, p.tw, sh, p.tiles, g);
       if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     }
     if ((e = tstart(c, 1)) != hipSuccess) return hip_check(c, e, "timing event");
-    hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
-                       c->stream, p.W, p.tw, l.ntz, g);
+    if constexpr (C::YC)
+      hipLaunchKernelGGL(ns::f_ycurl<typename C::Y>, dim3(2 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
+                         c->stream, p.W, p.tw, l.ntz, g);
+    else
+      hipLaunchKernelGGL((ns::f_ypass<typename C::Y, +1>), dim3(6 * N * l.ntz), dim3(ns::kFastL * C::Y::TPL), 0,
+                         c->stream, p.W, p.tw, l.ntz, g);
     if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
     if ((e = tstart(c, 2)) != hipSuccess) return hip_check(c, e, "timing event");
     hipLaunchKernelGGL((ns::f_zcross<typename C::Z, P>), dim3(N * N / P), dim3(P * C::Z::TPL), 0, c->stream,
@@ -55,8 +59,8 @@ ns_status eval_fast(ns_ctx* c, const Cx<float>* in, ns::Lay lin, const ns::Shift
   const int nblk = a.full ? N * l.ntzf : ntiles;
   if ((e = tstart(c, FEED ? 5 : 4)) != hipSuccess) return hip_check(c, e, "timing event");
   if (nblk > 0)
-    hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP, FEED>), dim3(nblk), dim3(ns::kFastL * C::XFwd::TPL), 0,
-                       c->stream, p.W, p.tw, sh, sh2, p.tiles, g, a);
+    hipLaunchKernelGGL((ns::f_xfwd<typename C::XFwd, OP, FEED, !C::YC>), dim3(nblk),
+                       dim3(ns::kFastL * C::XFwd::TPL), 0, c->stream, p.W, p.tw, sh, sh2, p.tiles, g, a);
   if ((e = tstop(c)) != hipSuccess) return hip_check(c, e, "timing event");
   return hip_check(c, hipGetLastError(), "nonlinear-term launch");
 }
@@ -92,7 +96,7 @@ ns_status adj_eval_fast(ns_ctx* c, const Cx<float>* st, ns::Lay lst, const ns::S
   constexpr int N = C::N, P = C::PZA;
   const int ntiles = l.ntiles_active;
   if (ntiles > 0) {
-    hipLaunchKernelGGL(ns::f_xinv<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
+    hipLaunchKernelGGL((ns::f_xinv<typename C::XInv, true>), dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
                        c->stream, st, lst, p.W, p.tw, sh, p.tiles, g);
     hipLaunchKernelGGL(ns::f_xlam<typename C::XInv>, dim3(ntiles), dim3(ns::kFastL * C::XInv::TPL), 0,
                        c->stream, la, p.W, p.tw, sh, p.tiles, g);

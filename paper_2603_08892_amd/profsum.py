@@ -40,6 +40,9 @@ CSRC = os.path.join(PKG, "csrc")
 
 ELEM = 8           # bytes of one FP32 complex
 HBM_PEAK_GBS = 8000.0
+# Grid sizes whose step sequences form the vorticity in the y-inverse pass
+# (FastCfg YC in csrc/ns_fast.hpp): their x-inverse passes write five fields, not six.
+YC_SIZES = frozenset({128, 144, 256, 270})
 
 
 def geometry(n, k2max):
@@ -56,34 +59,37 @@ def geometry(n, k2max):
     return {"n": n, "kzn": kzn, "lines": A, "retained": R, "h": n // 2 + 1}
 
 
-def pass_bytes(g, operands=6.0):
+def pass_bytes(g, operands=6.0, yc=None):
     """Algorithmic HBM bytes per launch of each pass of a chained step (operands: stage
     operands read and outputs stored per x-forward stage, in retained-mode fields:
     6 for the PS-RK2 Heun stages (one operand read, one output stored, three
     components each), 7.5 on average over the four Lawson RK4 stages, which read one,
-    two, two and one operand and store one output each).
+    two, two and one operand and store one output each).  F = 5 fields on the active
+    lines between the x-inverse and y-inverse passes where the y-inverse pass forms
+    the vorticity (yc; by default for the sizes in YC_SIZES), else 6.
 
-    x_inverse          reads the 3 retained components, writes 6 fields on the active lines
+    x_inverse          reads the 3 retained components, writes F fields on the active lines
                        (only the first evaluation of a call runs it on its own)
-    y_inverse          reads the 6 fields on the active lines, writes the full (x, y) planes k_z < kzn
+    y_inverse          reads the F fields on the active lines, writes the 6 full (x, y) planes k_z < kzn
     z_fused            reads 6 and writes 3 fields on those planes
     y_forward          reads 3 fields on the planes, writes them on the active lines
     x_forward_epilogue the last stage of a call: reads 3 fields on the active lines and the
                        partial update (retained modes), writes the state's whole half spectrum
     x_forward_inverse  every other stage: reads 3 fields on the active lines and one stage
                        operand, writes one stage output (retained modes; S1 only feeds the
-                       next evaluation and is not stored), then the next evaluation's 6
+                       next evaluation and is not stored), then the next evaluation's F
                        fields on the active lines
     """
     n, A, R, kzn, h = g["n"], g["lines"], g["retained"], g["kzn"], g["h"]
     planes = n * n * kzn
+    f = 5 if (n in YC_SIZES if yc is None else yc) else 6
     return {
-        "x_inverse": (3 * R + 6 * A * n) * ELEM,
-        "y_inverse": (6 * A * n + 6 * planes) * ELEM,
+        "x_inverse": (3 * R + f * A * n) * ELEM,
+        "y_inverse": (f * A * n + 6 * planes) * ELEM,
         "z_fused": (6 * planes + 3 * planes) * ELEM,
         "y_forward": (3 * planes + 3 * A * n) * ELEM,
         "x_forward_epilogue": (3 * A * n + 3 * R + 3 * n * n * h) * ELEM,
-        "x_forward_inverse": int((9 * A * n + operands * R) * ELEM),
+        "x_forward_inverse": int(((3 + f) * A * n + operands * R) * ELEM),
     }
 
 
@@ -103,12 +109,14 @@ def classify(name):
         kern, n = m.group(1), int(m.group(2))
         if kern == "f_xinv":
             return n, "x_inverse"
+        if kern == "f_ycurl":
+            return n, "y_inverse"
         if kern == "f_ypass":
             return n, "y_inverse" if re.search(r"> >, 1>\(", name) else "y_forward"
         if kern == "f_zcross":
             return n, "z_fused"
         if kern == "f_xfwd":
-            feed = re.search(r"> >, -?\d+, (\d+)>\(", name)
+            feed = re.search(r"> >, -?\d+, (\d+)(?:, (?:true|false))?>\(", name)
             return n, "x_forward_inverse" if feed and feed.group(1) != "0" else "x_forward_epilogue"
         return n, {"f_xlam": "lam_x", "f_zadj": "z_adjoint", "f_xadj": "x_adjoint"}.get(kern, kern)
     m = re.match(r"(?:void )?ns::(k_\w+)<", name) or re.match(r"(?:void )?ns::(k_\w+)\(", name)

@@ -14,17 +14,24 @@ from paper_2603_08892_amd import profsum
 
 PLAN = "ns::LinePlan<256, 32, ns::Radices<8, 8, 4>, ns::Radices<4, 8, 8> >"
 NAMES = {
-    "x_inverse": f"void ns::f_xinv<{PLAN} >(ns::Cx<float> const*, ns::Lay, ns::Cx<float>*)",
-    "y_inverse": f"void ns::f_ypass<{PLAN}, 1>(ns::Cx<float>*, ns::Cx<float> const*, int, ns::Geom)",
+    "x_inverse": f"void ns::f_xinv<{PLAN}, false>(ns::Cx<float> const*, ns::Lay, ns::Cx<float>*)",
+    "y_inverse": f"void ns::f_ycurl<{PLAN} >(ns::Cx<float>*, ns::Cx<float> const*, int, ns::Geom)",
     "y_forward": f"void ns::f_ypass<{PLAN}, -1>(ns::Cx<float>*, ns::Cx<float> const*, int, ns::Geom)",
     "z_fused": f"void ns::f_zcross<{PLAN}, 8>(ns::Cx<float>*, ns::Cx<float> const*, ns::Geom)",
-    "x_forward_epilogue": f"void ns::f_xfwd<{PLAN}, 3, 0>(ns::Cx<float>*, ns::Cx<float> const*, ns::Shift)",
-    "x_forward_inverse": f"void ns::f_xfwd<{PLAN}, 2, 2>(ns::Cx<float>*, ns::Cx<float> const*, ns::Shift)",
+    "x_forward_epilogue": f"void ns::f_xfwd<{PLAN}, 3, 0, false>(ns::Cx<float>*, ns::Cx<float> const*, ns::Shift)",
+    "x_forward_inverse": f"void ns::f_xfwd<{PLAN}, 2, 2, false>(ns::Cx<float>*, ns::Cx<float> const*, ns::Shift)",
+}
+# the same passes of a size without the vorticity formed in the y-inverse pass
+OTHER = {
+    "x_inverse": f"void ns::f_xinv<{PLAN}, true>(ns::Cx<float> const*, ns::Lay, ns::Cx<float>*)",
+    "y_inverse": f"void ns::f_ypass<{PLAN}, 1>(ns::Cx<float>*, ns::Cx<float> const*, int, ns::Geom)",
+    "x_forward_epilogue": f"void ns::f_xfwd<{PLAN}, 3, 0, true>(ns::Cx<float>*, ns::Cx<float> const*, ns::Shift)",
+    "x_forward_inverse": f"void ns::f_xfwd<{PLAN}, 2, 1, true>(ns::Cx<float>*, ns::Cx<float> const*, ns::Shift)",
 }
 
 
 def test_classify_names():
-    for want, name in NAMES.items():
+    for want, name in list(NAMES.items()) + list(OTHER.items()):
         assert profsum.classify(name) == (256, want)
     assert profsum.classify("void ns::k_spectra<float>(ns::Cx<float> const*)") == (None, "k_spectra")
     assert profsum.classify("ns::k_budget_step(double const*, int)") == (None, "k_budget_step")
@@ -78,9 +85,24 @@ def test_pass_bytes_hand_count():
     retained = sum(1 for a in k for b in k for c in range(3) if a * a + b * b + c * c <= k2)
     lines = sum(1 for b in k for c in range(3) if b * b + c * c <= k2)
     assert (g["retained"], g["lines"], g["kzn"]) == (retained, lines, 3)
-    pb = profsum.pass_bytes(g)
+    pb = profsum.pass_bytes(g)  # 8 is not a size with the curl in the y-inverse pass
     planes = n * n * 3
     assert pb["z_fused"] == 9 * planes * 8
     assert pb["x_forward_inverse"] == (9 * lines * n + 6 * retained) * 8
     assert profsum.pass_bytes(g, 7.5)["x_forward_inverse"] == int((9 * lines * n + 7.5 * retained) * 8)
     assert np.isclose(pb["y_inverse"], (6 * lines * n + 6 * planes) * 8)
+    # five fields between the x-inverse and y-inverse passes instead of six
+    yc = profsum.pass_bytes(g, yc=True)
+    assert pb["x_forward_inverse"] - yc["x_forward_inverse"] == lines * n * 8
+    assert pb["x_inverse"] - yc["x_inverse"] == lines * n * 8
+    assert pb["y_inverse"] - yc["y_inverse"] == lines * n * 8
+    assert yc["z_fused"] == pb["z_fused"] and yc["y_forward"] == pb["y_forward"]
+
+
+def test_yc_sizes_match_the_kernel_configs():
+    """YC_SIZES names exactly the FastCfg configurations of csrc/ns_fast.hpp with YC on."""
+    text = open(f"{profsum.CSRC}/ns_fast.hpp").read()
+    cfgs = re.findall(r"using Fast(\d+) = FastCfg<([^;]*)>;", text)
+    assert len(cfgs) == 13
+    on = {int(n) for n, args in cfgs if args.replace(" ", "").endswith(",true")}
+    assert on == set(profsum.YC_SIZES)
