@@ -334,13 +334,17 @@ def test_energy_conservation_on_gpu():
                                        (270, 0.8, "sphere"), (360, 512 / 3 / 180, "sphere"),
                                        # few retained modes: one k_z tile, most rows pruned
                                        (160, 0.1, "sphere"), (270, 0.05, "sphere"), (360, 0.02, "cube"),
-                                       (144, 1.0, "rogallo")])
+                                       (144, 1.0, "rogallo"),
+                                       # the sizes whose y-inverse pass forms the curl, other truncations
+                                       (256, 1.0, "no_multiple_aliases"), (256, 2 / 3, "cube"),
+                                       (270, 1.0, "cube"), (144, 0.5, "no_multiple_aliases")])
 def test_specialised_passes_match_generic(n, ct, mask):
     """The compile-time FP32 passes (N = 64, 128, 144, 160, 192, 216, 240, 256, 270,
     324, 360, 384, 512; at 160, 240, 270 and 360 some butterflies of a stage are
-    predicated off) and the size-generic passes agree to FP32 round-off (each is
-    within ~5e-6 of the FP64 oracle), for the nonlinear term and two steps of every
-    scheme."""
+    predicated off; at 128, 144, 256 and 270 the x-inverse passes store five fields
+    and the y-inverse pass forms the vorticity, where the generic passes store six)
+    and the size-generic passes agree to FP32 round-off (each is within ~5e-6 of the
+    FP64 oracle), for the nonlinear term and two steps of every scheme."""
     print(f"[fast-vs-generic] n={n} ct={ct:.4f} mask={mask}", flush=True)
     nu, dt = 1 / 1600, 2e-3
     fast = _solver(n, ct, mask, nu=nu, seed=4)
@@ -358,7 +362,11 @@ def test_specialised_passes_match_generic(n, ct, mask):
             else:
                 s_.step_ps(ud, dt, 2, scheme)
         a, b = _host(ua), _host(ub)
-        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-6, scheme
+        # two FP32 paths, each within ~2e-6 of the FP64 oracle after two steps: on
+        # the 270^3 cube field at C_t = 1 (every mode retained, Nyquist rows
+        # included) rk2 measured 1.88e-6 (specialised) and 1.86e-6 (generic)
+        # against the oracle and 2.5e-6 between them
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 3e-6, scheme
 
 
 @pytest.mark.parametrize("n,ct,prec,variant,forced", [
