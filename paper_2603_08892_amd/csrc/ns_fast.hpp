@@ -35,8 +35,24 @@ constexpr int kFastLp = kFastL + 1;
 __device__ __forceinline__ Cx<float> ld_off(const Cx<float>* __restrict__ base, uint32_t off) {
   return *reinterpret_cast<const Cx<float>*>(reinterpret_cast<const char*>(base) + off * 8u);
 }
+// STREAM: a non-temporal store, for the scratch fields and the compact stage
+// buffers of the grids whose step works on far more than the 256 MB last-level
+// cache (stream_stores): each pass's output is read back only by the next pass,
+// mostly on other XCDs, so keeping it in cache buys nothing.  Measured per PS-RK2
+// random step: 5-9% faster at N = 240...512; at N <= 216 much of a step's data
+// is still found in that cache and the step was 5-17% slower.  Outputs in the
+// caller's layout (rows of N/2 + 1 elements, not whole 128-byte lines) take
+// plain stores: streamed partial lines made those passes 1.5 times slower.
+constexpr bool stream_stores(int n) { return n >= 240; }
+template <bool STREAM = false>
 __device__ __forceinline__ void st_off(Cx<float>* __restrict__ base, uint32_t off, Cx<float> v) {
-  *reinterpret_cast<Cx<float>*>(reinterpret_cast<char*>(base) + off * 8u) = v;
+  if constexpr (STREAM) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 w = {v.re, v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<f2*>(reinterpret_cast<char*>(base) + off * 8u));
+  } else {
+    *reinterpret_cast<Cx<float>*>(reinterpret_cast<char*>(base) + off * 8u) = v;
+  }
 }
 
 // Branch-free masked load: the offset is clamped to element 0 of the (valid)
@@ -187,7 +203,8 @@ f_xinv(const Cx<float>* __restrict__ S, Lay ls, Cx<float>* __restrict__ W, const
     if (col) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i)
-        if (F::out_ok(t, i)) st_off(W + f * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
+        if (F::out_ok(t, i))
+          st_off<stream_stores(N)>(W + f * g.wcomp, (uint32_t)F::out_pos(t, i) * ostep + obase, v[i]);
     }
   };
   F::run(uy, t, lv, tw);
@@ -246,7 +263,8 @@ f_ypass(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, G
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int p = F::out_pos(t, i);
-      if (F::out_ok(t, i) && (S > 0 || abs(kval(p, N)) <= yb)) st_off(base, (uint32_t)(p * g.kzp) + rbase, v[i]);
+      if (F::out_ok(t, i) && (S > 0 || abs(kval(p, N)) <= yb))
+        st_off<stream_stores(N)>(base, (uint32_t)(p * g.kzp) + rbase, v[i]);
     }
   }
 }
@@ -325,7 +343,7 @@ f_ycurl(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, int ntz, G
     if (col) {
 #pragma unroll
       for (int i = 0; i < EPT; ++i)
-        if (F::out_ok(t, i)) st_off(base, (uint32_t)(F::out_pos(t, i) * g.kzp) + rbase, v[i]);
+        if (F::out_ok(t, i)) st_off<stream_stores(N)>(base, (uint32_t)(F::out_pos(t, i) * g.kzp) + rbase, v[i]);
     }
   };
   F::run(va, t, lv, tw);
@@ -424,9 +442,9 @@ f_zcross(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Geom g) {
     const int k = idx % g.kzn, pp = idx / g.kzn;
     const Cx<float> c1 = sp[pp * N + k], c2 = sp[pp * N + ((N - k) % N)];
     const uint32_t off = (line0 + pp) * (uint32_t)g.kzp + k;
-    st_off(W, off, cx(0.5f * (c1.re + c2.re), 0.5f * (c1.im - c2.im)));
-    st_off(W + g.wcomp, off, cx(0.5f * (c1.im + c2.im), -0.5f * (c1.re - c2.re)));
-    st_off(W + 2 * g.wcomp, off, xb[pp * LP + k]);
+    st_off<stream_stores(N)>(W, off, cx(0.5f * (c1.re + c2.re), 0.5f * (c1.im - c2.im)));
+    st_off<stream_stores(N)>(W + g.wcomp, off, cx(0.5f * (c1.im + c2.im), -0.5f * (c1.re - c2.re)));
+    st_off<stream_stores(N)>(W + 2 * g.wcomp, off, xb[pp * LP + k]);
   }
 }
 
@@ -493,6 +511,9 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
   constexpr int CH = ((need0 && need1) || ((need0 || need1) && N <= 128)) ? (EPT + 1) / 2 : EPT;
   const LineTest keep = line_test(g, ky, kz);
   const bool line_kept = active && kz < g.kzn;
+  // streaming stores into the compact stage buffers only (rows of whole 128-byte lines)
+  const bool st0 = stream_stores(N) && a.lo0.pitch == g.kzp;
+  [[maybe_unused]] const bool st1 = stream_stores(N) && a.lo1.pitch == g.kzp;
   Cx<float> s0v[need0 ? 3 : 1][need0 ? CH : 1], s1v[need1 ? 3 : 1][need1 ? CH : 1];
   auto load_ops = [&](int c0) {
 #pragma unroll
@@ -634,8 +655,12 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
       } else {  // OP_EULAV
         v0 = scale(s0 + scale(s1 + Nv, dt * a.w), edt);
       }
-      if constexpr (use1) st_off(out1, io1, v1);
-      st_off(out0, io0, v0);
+      if constexpr (use1) {
+        if (st1) st_off<true>(out1, io1, v1);
+        else st_off(out1, io1, v1);
+      }
+      if (st0) st_off<true>(out0, io0, v0);
+      else st_off(out0, io0, v0);
       if constexpr (FEED == 1) nx[c][i] = v0;
       if constexpr (FEED == 2) nx[c][i] = v1;
     }
@@ -669,7 +694,8 @@ f_xfwd(Cx<float>* __restrict__ W, const Cx<float>* __restrict__ twg, Shift sh, S
       if (col) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
-          if (FI::out_ok(t, i)) st_off(W + f * g.wcomp, (uint32_t)FI::out_pos(t, i) * ostep + obase, v[i]);
+          if (FI::out_ok(t, i))
+            st_off<stream_stores(N)>(W + f * g.wcomp, (uint32_t)FI::out_pos(t, i) * ostep + obase, v[i]);
       }
     };
     FI::run(uy, t, lv, tw);
