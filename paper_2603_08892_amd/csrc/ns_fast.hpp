@@ -38,9 +38,10 @@ __device__ __forceinline__ Cx<float> ld_off(const Cx<float>* __restrict__ base, 
 // STREAM: a non-temporal store, for the scratch fields and the compact stage
 // buffers of the grids whose step works on far more than the 256 MB last-level
 // cache (stream_stores): each pass's output is read back only by the next pass,
-// mostly on other XCDs, so keeping it in cache buys nothing.  Measured per PS-RK2
-// random step: 5-9% faster at N = 240...512; at N <= 216 much of a step's data
-// is still found in that cache and the step was 5-17% slower.  Outputs in the
+// mostly on other XCDs, so keeping it in cache buys nothing.  Measured per step
+// (PS-RK2 random, RK4 at 512): 3-11% faster at N = 240...512, 256 gaining least;
+// at N <= 216 much of a step's data is still found in that cache and the step
+// was 5-17% slower.  Outputs in the
 // caller's layout (rows of N/2 + 1 elements, not whole 128-byte lines) take
 // plain stores: streamed partial lines made those passes 1.5 times slower.
 constexpr bool stream_stores(int n) { return n >= 240; }
