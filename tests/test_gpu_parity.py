@@ -373,10 +373,12 @@ def test_specialised_passes_match_generic(n, ct, mask):
     (24, 1.0, "fp64", "random", True), (24, 1.0, "fp64", "approx", False), (24, 1.0, "fp64", "exact", False),
     (24, 1.0, "fp64", "rk2", False), (24, 1.0, "fp64", "euler", False), (24, 1.0, "fp64", "euler_ps", False),
     (24, 1.0, "fp64", "exact8", False), (128, 1.0, "fp32", "random", True), (128, 1.0, "fp32", "approx", False),
-    (128, 1.0, "fp32", "exact", False), (192, 2 / 3, "fp32", "random", False), (64, 1.0, "fp32", "exact8", False)])
+    (128, 1.0, "fp32", "exact", False), (192, 2 / 3, "fp32", "random", False), (64, 1.0, "fp32", "exact8", False),
+    # streaming stores into the scratch fields and the compact stage buffers
+    (256, 1.0, "fp32", "random", True), (240, 1.0, "fp32", "exact", False), (270, 0.8, "fp32", "approx", False)])
 def test_multi_step_call_equals_single_steps(n, ct, prec, variant, forced):
     """k steps in one call (the state stays in the workspace between them) are
-    bit-identical to k calls of one step, and both match the oracle."""
+    bit-identical to k calls of one step, and both match the oracle (N <= 24)."""
     print(f"[multi-step] n={n} {prec} {variant} forced={forced}", flush=True)
     nu, dt, k = 0.01, 2e-3, 4
     s = _solver(n, ct, prec=prec, nu=nu, seed=31)
